@@ -1,0 +1,297 @@
+/*
+ * CPU ORACLE for D8 flow directions and D8 up-slope area -- TEST INFRASTRUCTURE.
+ *
+ * Only tests/, __graft_entry__.smoke() and bench.py's cpu_baseline leg may load
+ * this library.  The product path (the HIP library and its Python binding)
+ * never links, imports or calls it, and shares no code, header or table with
+ * it.
+ *
+ * Plain, single-threaded, obviously correct.  Floating-point sums are in fp64.
+ * Method: Barnes, Lehman & Mulla, "Distributed Parallel D8 Up-Slope Area
+ * Calculation in Digital Elevation Models", PDPTA 2011.
+ *
+ *   - Sec. 2, Eq. (1): A(p) = 1 + sum of A(i) over the neighbours i that drain
+ *     into p.  Sec. 2 also allows per-cell weights, so A(p) = w(p) + sum A(i).
+ *   - Sec. 1 (the D8 function of O'Callaghan & Mark): each cell sends all of its
+ *     flow to the lowest of its eight neighbours; flows join but never split,
+ *     so the flow graph is a forest.
+ *   - Sec. 3, Alg. 1 (dependency counting) and Alg. 2 (queue-driven internal
+ *     up-slope area) evaluate Eq. (1) in dependency order; here they run on the
+ *     whole DEM as one partition with a plain FIFO queue (Kahn's order).
+ *
+ * Readings where the paper is silent (each listed in the design doc):
+ *   - "lowest" neighbour, strict '<', scanned in the order E,NE,N,NW,W,SW,S,SE;
+ *     the first minimum wins; no strictly lower neighbour -> outlet (code 8).
+ *   - row 0 is north; E = (r, c+1), N = (r-1, c).
+ *   - every valid DEM-boundary cell, and every valid cell 8-adjacent to NoData
+ *     (NaN), is an outlet (code 8); NaN cells get code 255 and area 0.
+ *
+ * Direction codes: 0 E, 1 NE, 2 N, 3 NW, 4 W, 5 SW, 6 S, 7 SE, 8 outlet,
+ * 255 NoData.
+ *
+ * Parity status: flowdirs, accumulation (u32 and f64), backward and brute force
+ * are pinned by tests that do not reuse this code (plane closed forms, the
+ * serpentine closed forms, pure-Python brute force on tiny grids, a hand-worked
+ * fixture, the recursion identity, the outlet-sum invariant, linearity and the
+ * adjoint dot-product identity).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Oracle status values (independent of the product's status enum). */
+#define ORC_OK 0
+#define ORC_BADDIR 4 /* code not in {0..8, 255}, or a target off-grid / into NoData */
+#define ORC_CYCLE 5  /* the direction field is not a forest */
+#define ORC_NOMEM 2
+
+static const int ODR[8] = {0, -1, -1, -1, 0, 1, 1, 1};
+static const int ODC[8] = {1, 1, 0, -1, -1, -1, 0, 1};
+
+/* D8 "lowest of eight" direction field (Sec. 1; tie and edge readings above). */
+int orc_flowdirs(const float* z, int64_t H, int64_t W, uint8_t* dirs) {
+  for (int64_t r = 0; r < H; ++r) {
+    for (int64_t c = 0; c < W; ++c) {
+      int64_t i = r * W + c;
+      float v = z[i];
+      if (isnan(v)) { dirs[i] = 255; continue; }
+      if (r == 0 || c == 0 || r == H - 1 || c == W - 1) { dirs[i] = 8; continue; }
+      int nan_adj = 0;
+      for (int d = 0; d < 8; ++d)
+        if (isnan(z[(r + ODR[d]) * W + c + ODC[d]])) nan_adj = 1;
+      if (nan_adj) { dirs[i] = 8; continue; }
+      float best = v;
+      int k = 8;
+      for (int d = 0; d < 8; ++d) {
+        float n = z[(r + ODR[d]) * W + c + ODC[d]];
+        if (n < best) { best = n; k = d; }
+      }
+      dirs[i] = (uint8_t)k;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Target of cell i, or -1 for an outlet / NoData; -2 for an invalid field. */
+static int64_t target_of(const uint8_t* dirs, int64_t H, int64_t W, int64_t i) {
+  uint8_t k = dirs[i];
+  if (k == 8 || k == 255) return -1;
+  if (k > 8) return -2;
+  int64_t r = i / W + ODR[k], c = i % W + ODC[k];
+  if (r < 0 || r >= H || c < 0 || c >= W) return -2;
+  int64_t t = r * W + c;
+  if (dirs[t] == 255) return -2;
+  return t;
+}
+
+/* Checks the field; fills tgt[] (int64 per cell, -1 = none) and indeg[].
+ * indeg counts the cells that drain into each cell (Alg. 1's dependency count). */
+static int prepare(const uint8_t* dirs, int64_t H, int64_t W, int64_t* tgt, uint8_t* indeg,
+                   int64_t* nvalid) {
+  const int64_t N = H * W;
+  int64_t nv = 0;
+  memset(indeg, 0, (size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t t = target_of(dirs, H, W, i);
+    if (t == -2) return ORC_BADDIR;
+    tgt[i] = t;
+    if (dirs[i] != 255) ++nv;
+    if (t >= 0) indeg[t]++;
+  }
+  *nvalid = nv;
+  return ORC_OK;
+}
+
+/* Kahn order of all valid cells (upstream before downstream); returns status. */
+static int kahn_order(const uint8_t* dirs, int64_t N, const int64_t* tgt, uint8_t* indeg,
+                      int64_t nvalid, uint32_t* order) {
+  int64_t head = 0, tail = 0;
+  for (int64_t i = 0; i < N; ++i)
+    if (dirs[i] != 255 && indeg[i] == 0) order[tail++] = (uint32_t)i;
+  while (head < tail) {
+    uint32_t u = order[head++];
+    int64_t t = tgt[u];
+    if (t >= 0 && --indeg[t] == 0) order[tail++] = (uint32_t)t;
+  }
+  return tail == nvalid ? ORC_OK : ORC_CYCLE;
+}
+
+/* Eq. (1) with unit weights, uint32 counts, Alg. 1 + Alg. 2 with a FIFO queue. */
+int orc_accum_u32(const uint8_t* dirs, int64_t H, int64_t W, uint32_t* A) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  uint32_t* q = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  int64_t* tgt = NULL;
+  int st = ORC_NOMEM;
+  int64_t nvalid = 0;
+  /* targets are recomputed on the fly to keep memory at ~10 B/cell */
+  if (!indeg || !q) goto out;
+  memset(indeg, 0, (size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t t = target_of(dirs, H, W, i);
+    if (t == -2) { st = ORC_BADDIR; goto out; }
+    if (dirs[i] != 255) ++nvalid;
+    if (t >= 0) indeg[t]++;
+    A[i] = dirs[i] == 255 ? 0u : 1u;
+  }
+  {
+    int64_t head = 0, tail = 0;
+    for (int64_t i = 0; i < N; ++i)
+      if (dirs[i] != 255 && indeg[i] == 0) q[tail++] = (uint32_t)i;
+    while (head < tail) {
+      uint32_t u = q[head++];
+      int64_t t = target_of(dirs, H, W, u);
+      if (t >= 0) {
+        A[t] += A[u];
+        if (--indeg[t] == 0) q[tail++] = (uint32_t)t;
+      }
+    }
+    st = (tail == nvalid) ? ORC_OK : ORC_CYCLE;
+  }
+out:
+  free(indeg); free(q); free(tgt);
+  return st;
+}
+
+/* Eq. (1) with weights w (float32 in, NULL = unit), fp64 sums. */
+int orc_accum_f64(const uint8_t* dirs, int64_t H, int64_t W, const float* w, double* A) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  int64_t* tgt = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  uint32_t* order = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  int st = ORC_NOMEM;
+  int64_t nvalid = 0;
+  if (!indeg || !tgt || !order) goto out;
+  st = prepare(dirs, H, W, tgt, indeg, &nvalid);
+  if (st != ORC_OK) goto out;
+  for (int64_t i = 0; i < N; ++i) A[i] = dirs[i] == 255 ? 0.0 : (w ? (double)w[i] : 1.0);
+  st = kahn_order(dirs, N, tgt, indeg, nvalid, order);
+  if (st != ORC_OK) goto out;
+  for (int64_t j = 0; j < nvalid; ++j) {
+    uint32_t u = order[j];
+    if (tgt[u] >= 0) A[tgt[u]] += A[u];
+  }
+out:
+  free(indeg); free(tgt); free(order);
+  return st;
+}
+
+/* Adjoint of the weighted accumulation: A = (I - P)^-1 w, so the gradient of a
+ * loss with respect to w is (I - P)^-T g, i.e. G(c) = g(c) + G(target(c)):
+ * the sum of g along c's downstream path, c included.  Evaluated in reverse
+ * Kahn order (downstream before upstream).  g is float32 (NULL = unit). */
+int orc_backward_f64(const uint8_t* dirs, int64_t H, int64_t W, const float* g, double* G) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  int64_t* tgt = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  uint32_t* order = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  int st = ORC_NOMEM;
+  int64_t nvalid = 0;
+  if (!indeg || !tgt || !order) goto out;
+  st = prepare(dirs, H, W, tgt, indeg, &nvalid);
+  if (st != ORC_OK) goto out;
+  st = kahn_order(dirs, N, tgt, indeg, nvalid, order);
+  if (st != ORC_OK) goto out;
+  for (int64_t i = 0; i < N; ++i) G[i] = dirs[i] == 255 ? 0.0 : (g ? (double)g[i] : 1.0);
+  for (int64_t j = nvalid - 1; j >= 0; --j) {
+    uint32_t u = order[j];
+    if (tgt[u] >= 0) G[u] += G[tgt[u]];
+  }
+out:
+  free(indeg); free(tgt); free(order);
+  return st;
+}
+
+/* Same as orc_backward_f64 but with fp64 upstream gradients. */
+int orc_backward_f64d(const uint8_t* dirs, int64_t H, int64_t W, const double* g, double* G) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  int64_t* tgt = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  uint32_t* order = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  int st = ORC_NOMEM;
+  int64_t nvalid = 0;
+  if (!indeg || !tgt || !order) goto out;
+  st = prepare(dirs, H, W, tgt, indeg, &nvalid);
+  if (st != ORC_OK) goto out;
+  st = kahn_order(dirs, N, tgt, indeg, nvalid, order);
+  if (st != ORC_OK) goto out;
+  for (int64_t i = 0; i < N; ++i) G[i] = dirs[i] == 255 ? 0.0 : g[i];
+  for (int64_t j = nvalid - 1; j >= 0; --j) {
+    uint32_t u = order[j];
+    if (tgt[u] >= 0) G[u] += G[tgt[u]];
+  }
+out:
+  free(indeg); free(tgt); free(order);
+  return st;
+}
+
+/* Same as orc_accum_f64 but with fp64 weights. */
+int orc_accum_f64d(const uint8_t* dirs, int64_t H, int64_t W, const double* w, double* A) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  int64_t* tgt = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  uint32_t* order = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  int st = ORC_NOMEM;
+  int64_t nvalid = 0;
+  if (!indeg || !tgt || !order) goto out;
+  st = prepare(dirs, H, W, tgt, indeg, &nvalid);
+  if (st != ORC_OK) goto out;
+  for (int64_t i = 0; i < N; ++i) A[i] = dirs[i] == 255 ? 0.0 : w[i];
+  st = kahn_order(dirs, N, tgt, indeg, nvalid, order);
+  if (st != ORC_OK) goto out;
+  for (int64_t j = 0; j < nvalid; ++j) {
+    uint32_t u = order[j];
+    if (tgt[u] >= 0) A[tgt[u]] += A[u];
+  }
+out:
+  free(indeg); free(tgt); free(order);
+  return st;
+}
+
+/* Brute force straight from the physical definition in Sec. 2: every valid cell
+ * s adds its weight to every cell its flow passes through, s included.
+ * O(N * path length); tiny grids only.  Guard: a path longer than N cells means
+ * a cycle. */
+int orc_bruteforce_f64(const uint8_t* dirs, int64_t H, int64_t W, const float* w, double* A) {
+  const int64_t N = H * W;
+  for (int64_t i = 0; i < N; ++i) A[i] = 0.0;
+  for (int64_t s = 0; s < N; ++s) {
+    if (dirs[s] == 255) continue;
+    double ws = w ? (double)w[s] : 1.0;
+    int64_t u = s, steps = 0;
+    for (;;) {
+      A[u] += ws;
+      int64_t t = target_of(dirs, H, W, u);
+      if (t == -2) return ORC_BADDIR;
+      if (t < 0) break;
+      if (++steps > N) return ORC_CYCLE;
+      u = t;
+    }
+  }
+  return ORC_OK;
+}
+
+/* Longest upstream dependency chain ending at each cell (cells, inclusive);
+ * returns the maximum over the DEM, or -1 on error. */
+int64_t orc_depth(const uint8_t* dirs, int64_t H, int64_t W) {
+  const int64_t N = H * W;
+  uint8_t* indeg = (uint8_t*)malloc((size_t)N);
+  int64_t* tgt = (int64_t*)malloc((size_t)N * sizeof(int64_t));
+  uint32_t* order = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
+  uint32_t* d = (uint32_t*)calloc((size_t)N, sizeof(uint32_t));
+  int64_t best = -1, nvalid = 0;
+  if (!indeg || !tgt || !order || !d) goto out;
+  if (prepare(dirs, H, W, tgt, indeg, &nvalid) != ORC_OK) goto out;
+  if (kahn_order(dirs, N, tgt, indeg, nvalid, order) != ORC_OK) goto out;
+  best = 0;
+  for (int64_t j = 0; j < nvalid; ++j) {
+    uint32_t u = order[j];
+    d[u] += 1;
+    if (d[u] > best) best = d[u];
+    if (tgt[u] >= 0 && d[tgt[u]] < d[u]) d[tgt[u]] = d[u];
+  }
+out:
+  free(indeg); free(tgt); free(order); free(d);
+  return best;
+}

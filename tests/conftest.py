@@ -1,0 +1,24 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")
+    config.addinivalue_line("markers", "slow: full-size workload (minutes of input generation)")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _host_helpers_built():
+    # gcc-only host helpers (oracle, DEM fill); cheap, no GPU involved.
+    import demgen
+    import oracle
+
+    demgen.build_fill()
+    oracle.build()
+    yield
