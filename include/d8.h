@@ -1,0 +1,169 @@
+/*
+ * d8.h -- C ABI of the MI355X (gfx950) D8 flow-direction and up-slope-area library.
+ *
+ * Method: Barnes, Lehman & Mulla, "Distributed Parallel D8 Up-Slope Area
+ * Calculation in Digital Elevation Models" (PDPTA 2011).
+ *   - Sec. 2, Eq. (1): up-slope area A(p) = w(p) + sum of A(i) over the cells i
+ *     that drain into p (w = 1 gives the cell count; Sec. 2 allows weights).
+ *   - Sec. 1: the D8 function sends all of a cell's flow to the lowest of its
+ *     eight neighbours, so flows join but never split (the field is a forest).
+ *   - Sec. 3: the DEM is partitioned; each part computes its internal area with
+ *     the inflows from other parts left as unknowns (Alg. 1-4), one solve over
+ *     the parts' border graph resolves them (Alg. 5-6), and each part adds the
+ *     resolved inflows along its downstream paths (Alg. 7-8).  Here the parts
+ *     are square tiles of one GPU's DEM and the border graph is solved on the
+ *     GPU in O(log depth) rounds.
+ *
+ * Conventions shared by every entry point
+ *   Grids are row-major, `rows` x `cols`, contiguous, row 0 = north edge,
+ *   column 0 = west edge.  NoData = NaN in a DEM, code 255 in a direction field.
+ *   Direction codes (uint8): 0 E (0,+1), 1 NE (-1,+1), 2 N (-1,0), 3 NW (-1,-1),
+ *   4 W (0,-1), 5 SW (+1,-1), 6 S (+1,0), 7 SE (+1,+1), 8 outlet, 255 NoData.
+ *   A cell with code 0..7 drains into the neighbour at that offset.
+ *
+ * Ownership and ordering
+ *   Every array argument is a DEVICE pointer owned by the caller (the library
+ *   never allocates device memory).  Scratch memory is a caller-owned device
+ *   workspace of at least d8_*_workspace_bytes() bytes, 256-byte aligned.
+ *   Outputs must not alias inputs.  Every call only enqueues work on `stream`
+ *   (a hipStream_t; NULL = the default stream) and returns; there is no hidden
+ *   synchronisation, so calls may be captured into a HIP graph.
+ *
+ * Errors
+ *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, unsupported
+ *   tile, workspace too small, a HIP launch failure) are returned at once and
+ *   nothing is enqueued.  Data errors found on the device (a direction code
+ *   outside {0..8, 255}; a target off the grid or into NoData; a cycle) are
+ *   OR-ed into a status word in the workspace; the computation still runs to
+ *   completion and the outputs of affected cells are unspecified.  Read the
+ *   word with d8_device_status() after the call.
+ */
+#ifndef D8_H_
+#define D8_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  D8_OK = 0,
+  D8_EINVAL = 1,        /* bad argument */
+  D8_ENOMEM = 2,        /* workspace too small */
+  D8_EHIP = 3,          /* a HIP runtime call or launch failed */
+  D8_EBADDIR = 4,       /* device: bad direction code or target off-grid / into NoData */
+  D8_ECYCLE = 5,        /* device: the direction field contains a cycle */
+  D8_EUNSUPPORTED = 6   /* combination not supported by this build */
+} d8_status;
+
+enum { D8_E = 0, D8_NE, D8_N, D8_NW, D8_W, D8_SW, D8_S, D8_SE, D8_NONE = 8, D8_NODATA = 255 };
+
+typedef enum { D8_U32 = 0, D8_F32 = 1 } d8_dtype;
+
+/* One DEM of a batch: element offset of its first cell in the packed buffers
+ * (the same offset is used for dem, dirs, weights, outputs and gradients) and
+ * its shape.  Host array for *_workspace_bytes and d8_plan_*, device array for
+ * the batched launches. */
+typedef struct {
+  int64_t offset;
+  int32_t rows;
+  int32_t cols;
+} d8_desc;
+
+/* Tile sides accepted by `tile` (0 = library default, currently 64). */
+#define D8_TILE_DEFAULT 0
+
+/* ------------------------------------------------------------------------ */
+/* Flow directions (Sec. 1 "lowest of eight"; Sec. 3 halo of neighbour rows). */
+
+/* dem: float32 [rows*cols]; dirs: uint8 [rows*cols] (output).
+ * A NaN cell gets 255.  A valid cell on the DEM boundary or 8-adjacent to NaN
+ * gets 8.  Otherwise the neighbours are scanned E,NE,N,NW,W,SW,S,SE and the
+ * first one strictly lower than every earlier candidate and than the cell
+ * wins; with no strictly lower neighbour the cell gets 8.  Exact (compares
+ * only).  No workspace. */
+d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Up-slope area (Eq. 1) over a direction field. */
+
+/* Bytes of workspace d8_accum / d8_accum_backward need for this shape and tile
+ * (0 = default).  Returns 0 for an invalid shape or tile. */
+size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile);
+
+/* dirs: uint8 codes [rows*cols].
+ * weights: float32 [rows*cols], or NULL for unit weights.
+ * out_dtype: D8_U32 (counts; requires weights == NULL) or D8_F32.
+ * out: uint32 or float32 [rows*cols] (output).  NoData cells get 0.
+ *   Counts are exact.  Weighted sums are carried as float32 pairs (hi, lo)
+ *   with error-free transformations inside tiles and in fp64 across tiles;
+ *   out = fl32(hi + lo).
+ * out_lo: NULL, or float32 [rows*cols] receiving the rounding residual, so
+ *   that out + out_lo carries about 48 significant bits (weighted only).
+ * ws / ws_bytes: workspace.  tile: 0, 32, 64 or 128. */
+d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights,
+                   d8_dtype out_dtype, void* out, float* out_lo, void* ws, size_t ws_bytes, int tile,
+                   void* stream);
+
+/* Adjoint of the weighted accumulation.  The map w -> A is linear,
+ * A = (I - P)^-1 w with P the D8 drainage matrix, so for a loss with
+ * dL/dA = grad_out the gradient is grad_weights = (I - P)^-T grad_out:
+ * grad_weights(c) = sum of grad_out over the cells on c's downstream path,
+ * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0. */
+d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
+                            float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched: n DEMs of uneven shapes packed in one buffer, one set of launches
+ * for the whole batch.  host_desc / dev_desc describe the same n DEMs (host
+ * and device copies).  A DEM may not exceed 2^31-1 cells.  `waves` is the
+ * number of 64-lane waves per tile workgroup (0 = default); see
+ * d8_autotune_batched. */
+
+size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile);
+
+/* Flow directions for every DEM of the batch (same rule as d8_flowdirs).
+ * ws: workspace of d8_batched_workspace_bytes(host_desc, n, 0) bytes (only
+ * its header and DEM table are used). */
+d8_status d8_flowdirs_batched(const float* dem_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
+                              int32_t n, uint8_t* dirs_packed, void* ws, size_t ws_bytes, void* stream);
+
+d8_status d8_accum_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
+                           int32_t n, const float* w_packed, d8_dtype out_dtype, void* out_packed,
+                           float* out_lo_packed, void* ws, size_t ws_bytes, int tile, int waves,
+                           void* stream);
+
+d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* host_desc,
+                                    const d8_desc* dev_desc, int32_t n, const float* g_packed,
+                                    float* gw_packed, void* ws, size_t ws_bytes, int tile, int waves,
+                                    void* stream);
+
+/* Times the batched forward+backward for every supported (tile, waves) pair on
+ * the given inputs (synchronising `stream`) and writes the fastest pair.
+ * Outputs are scratch.  ws must be sized for the largest tile side tried
+ * (d8_batched_workspace_bytes with tile 32). */
+d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
+                              int32_t n, const float* w_packed, float* out_scratch, float* g_scratch,
+                              void* ws, size_t ws_bytes, int* best_tile, int* best_waves, float* best_ms,
+                              void* stream);
+
+/* ------------------------------------------------------------------------ */
+
+/* Synchronises `stream`, then reads the device status word of `ws` into
+ * *status_out (D8_OK, or the first of D8_EBADDIR / D8_ECYCLE found) and
+ * returns D8_OK, or D8_EHIP if the read failed. */
+d8_status d8_device_status(const void* ws, void* stream, int32_t* status_out);
+
+/* Static text for a status code. */
+const char* d8_strerror(d8_status s);
+
+/* Library version string. */
+const char* d8_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* D8_H_ */

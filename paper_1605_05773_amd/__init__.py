@@ -1,0 +1,293 @@
+"""D8 flow directions and up-slope area on MI355X (gfx950).
+
+Thin Python binding over the C ABI in include/d8.h (libd8.so, built in-tree by
+build_lib.py).  Every step of the computation runs in the library's HIP
+kernels; this module only marshals arguments: PyTorch supplies device memory
+(the caching allocator) and the current HIP stream.  There is no CPU fallback:
+if libd8.so is missing every call raises.
+
+    dirs = flowdirs(dem)                       # uint8 codes, same shape
+    A = accum(dirs)                            # uint32 counts (Eq. 1, w = 1)
+    A = accum(dirs, weights)                   # float32 weighted
+    A = D8Accum.apply(dirs, weights)           # differentiable in weights
+    g = accum_backward(dirs, grad_out)         # adjoint
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libd8.so")
+
+D8_OK, D8_EINVAL, D8_ENOMEM, D8_EHIP, D8_EBADDIR, D8_ECYCLE, D8_EUNSUPPORTED = range(7)
+D8_U32, D8_F32 = 0, 1
+NONE, NODATA = 8, 255
+
+_lib = None
+
+
+class D8Error(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        msg = _lib.d8_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+        self.status = status
+
+
+class d8_desc(ctypes.Structure):
+    _fields_ = [("offset", ctypes.c_int64), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32)]
+
+
+def lib():
+    """The loaded libd8.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+        sig = {
+            "d8_flowdirs": ([P, I64, I64, P, P], I32),
+            "d8_workspace_bytes": ([I64, I64, I32], SZ),
+            "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
+            "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
+            "d8_batched_workspace_bytes": ([P, I32, I32], SZ),
+            "d8_flowdirs_batched": ([P, P, P, I32, P, P, SZ, P], I32),
+            "d8_accum_batched": ([P, P, P, I32, P, I32, P, P, P, SZ, I32, I32, P], I32),
+            "d8_accum_backward_batched": ([P, P, P, I32, P, P, P, SZ, I32, I32, P], I32),
+            "d8_autotune_batched": ([P, P, P, I32, P, P, P, P, SZ, P, P, P, P], I32),
+            "d8_device_status": ([P, P, P], I32),
+            "d8_strerror": ([I32], ctypes.c_char_p),
+            "d8_version": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+EXPORTED = (
+    "d8_flowdirs", "d8_workspace_bytes", "d8_accum", "d8_accum_backward", "d8_batched_workspace_bytes",
+    "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
+    "d8_device_status", "d8_strerror", "d8_version",
+)
+
+
+def _check(st: int, what: str):
+    if st != D8_OK:
+        raise D8Error(st, what)
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _dev_tensor(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
+_ws_cache: dict = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached device workspace of at least nbytes (256-byte aligned)."""
+    device = torch.device(device)
+    key = device.index if device.index is not None else torch.cuda.current_device()
+    cur = _ws_cache.get(key)
+    if cur is None or cur.numel() < nbytes + 256:
+        cur = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        _ws_cache[key] = cur
+    base = cur.data_ptr()
+    pad = (-base) % 256
+    return cur[pad:pad + nbytes]
+
+
+def flowdirs(dem: torch.Tensor) -> torch.Tensor:
+    """D8 'lowest of eight' codes of a float32 DEM (NaN = NoData)."""
+    dem = _dev_tensor(dem, torch.float32, "dem")
+    if dem.dim() != 2:
+        raise ValueError("dem must be 2-D")
+    out = torch.empty(dem.shape, dtype=torch.uint8, device=dem.device)
+    _check(lib().d8_flowdirs(dem.data_ptr(), dem.shape[0], dem.shape[1], out.data_ptr(), _stream(dem.device)),
+           "d8_flowdirs")
+    return out
+
+
+def workspace_bytes(rows: int, cols: int, tile: int = 0) -> int:
+    n = lib().d8_workspace_bytes(rows, cols, tile)
+    if n == 0:
+        raise D8Error(D8_EINVAL, "d8_workspace_bytes")
+    return n
+
+
+def accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, *, tile: int = 0, out: torch.Tensor | None = None,
+          out_lo: torch.Tensor | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Up-slope area of every cell (Eq. 1): uint32 counts, or float32 if weighted."""
+    dirs = _dev_tensor(dirs, torch.uint8, "dirs")
+    H, W = dirs.shape
+    if weights is None and out_lo is None and (out is None or out.dtype == torch.uint32):
+        dt = D8_U32
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.uint32, device=dirs.device)
+    else:
+        dt = D8_F32
+        if weights is not None:
+            weights = _dev_tensor(weights, torch.float32, "weights")
+            if weights.shape != dirs.shape:
+                raise ValueError("weights shape")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.float32, device=dirs.device)
+    if out_lo is not None:
+        _dev_tensor(out_lo, torch.float32, "out_lo")
+    nb = workspace_bytes(H, W, tile)
+    if ws is None:
+        ws = workspace(nb, dirs.device)
+    _check(lib().d8_accum(dirs.data_ptr(), H, W, None if weights is None else weights.data_ptr(), dt,
+                          out.data_ptr(), None if out_lo is None else out_lo.data_ptr(), ws.data_ptr(), ws.numel(),
+                          tile, _stream(dirs.device)), "d8_accum")
+    _maybe_debug_check(ws, dirs.device)
+    return out
+
+
+def accum_backward(dirs: torch.Tensor, grad_out: torch.Tensor, *, tile: int = 0,
+                   ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Gradient of a loss w.r.t. the weights given dL/dA: sums of grad_out along
+    each cell's downstream path."""
+    dirs = _dev_tensor(dirs, torch.uint8, "dirs")
+    grad_out = _dev_tensor(grad_out, torch.float32, "grad_out")
+    H, W = dirs.shape
+    gw = torch.empty((H, W), dtype=torch.float32, device=dirs.device)
+    nb = workspace_bytes(H, W, tile)
+    if ws is None:
+        ws = workspace(nb, dirs.device)
+    _check(lib().d8_accum_backward(dirs.data_ptr(), H, W, grad_out.data_ptr(), gw.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), tile, _stream(dirs.device)), "d8_accum_backward")
+    _maybe_debug_check(ws, dirs.device)
+    return gw
+
+
+def device_status(ws: torch.Tensor | None = None, device=None) -> int:
+    """Synchronises and returns the device status of the last call on ws
+    (D8_OK, D8_EBADDIR or D8_ECYCLE)."""
+    if ws is None:
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        ws = _ws_cache[dev.index if dev.index is not None else torch.cuda.current_device()]
+        base = ws.data_ptr()
+        ws = ws[(-base) % 256:]
+    st = ctypes.c_int32(0)
+    _check(lib().d8_device_status(ws.data_ptr(), _stream(ws.device), ctypes.byref(st)), "d8_device_status")
+    return st.value
+
+
+def _maybe_debug_check(ws, device):
+    if os.environ.get("D8_DEBUG") == "1":
+        st = device_status(ws)
+        if st != D8_OK:
+            raise D8Error(st, "device")
+
+
+class D8Accum(torch.autograd.Function):
+    """Weighted up-slope area, differentiable in the weights.
+
+    forward(dirs, w) -> A (float32); backward(dL/dA) -> dL/dw through the
+    adjoint kernel (no gradient for dirs)."""
+
+    @staticmethod
+    def forward(ctx, dirs, weights, tile: int = 0):
+        ctx.save_for_backward(dirs)
+        ctx.tile = tile
+        return accum(dirs, weights.contiguous(), tile=tile)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (dirs,) = ctx.saved_tensors
+        gw = accum_backward(dirs, grad_out.contiguous().to(torch.float32), tile=ctx.tile)
+        return None, gw, None
+
+
+# ------------------------------------------------------------------ batched --
+
+class Batch:
+    """n DEMs of uneven shapes packed into one device buffer."""
+
+    def __init__(self, shapes, device):
+        self.shapes = [(int(r), int(c)) for r, c in shapes]
+        self.device = torch.device(device)
+        offs, o = [], 0
+        for r, c in self.shapes:
+            offs.append(o)
+            o += r * c
+        self.offsets = offs
+        self.total = o
+        self.n = len(self.shapes)
+        self.host_desc = (d8_desc * self.n)(*[d8_desc(off, r, c) for off, (r, c) in zip(offs, self.shapes)])
+        raw = torch.frombuffer(bytearray(ctypes.string_at(ctypes.addressof(self.host_desc),
+                                                          ctypes.sizeof(self.host_desc))), dtype=torch.uint8)
+        self.dev_desc = raw.to(self.device)
+
+    def pack(self, arrays, dtype):
+        out = torch.empty(self.total, dtype=dtype, device=self.device)
+        for off, (r, c), a in zip(self.offsets, self.shapes, arrays):
+            out[off:off + r * c].copy_(torch.as_tensor(a).reshape(-1).to(dtype), non_blocking=False)
+        return out
+
+    def unpack(self, packed):
+        return [packed[off:off + r * c].view(r, c) for off, (r, c) in zip(self.offsets, self.shapes)]
+
+    def workspace_bytes(self, tile=0):
+        n = lib().d8_batched_workspace_bytes(ctypes.addressof(self.host_desc), self.n, tile)
+        if n == 0:
+            raise D8Error(D8_EINVAL, "d8_batched_workspace_bytes")
+        return n
+
+
+def flowdirs_batched(batch: Batch, dem_packed: torch.Tensor, ws=None) -> torch.Tensor:
+    dem_packed = _dev_tensor(dem_packed, torch.float32, "dem_packed")
+    out = torch.empty(batch.total, dtype=torch.uint8, device=batch.device)
+    nb = batch.workspace_bytes(0)
+    ws = workspace(nb, batch.device) if ws is None else ws
+    _check(lib().d8_flowdirs_batched(dem_packed.data_ptr(), ctypes.addressof(batch.host_desc),
+                                     batch.dev_desc.data_ptr(), batch.n, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     _stream(batch.device)), "d8_flowdirs_batched")
+    return out
+
+
+def accum_batched(batch: Batch, dirs_packed, w_packed=None, *, tile=0, waves=0, out=None, out_lo=None, ws=None):
+    dirs_packed = _dev_tensor(dirs_packed, torch.uint8, "dirs_packed")
+    if w_packed is None and out_lo is None and (out is None or out.dtype == torch.uint32):
+        dt = D8_U32
+        out = torch.empty(batch.total, dtype=torch.uint32, device=batch.device) if out is None else out
+    else:
+        dt = D8_F32
+        out = torch.empty(batch.total, dtype=torch.float32, device=batch.device) if out is None else out
+    nb = batch.workspace_bytes(tile)
+    ws = workspace(nb, batch.device) if ws is None else ws
+    _check(lib().d8_accum_batched(dirs_packed.data_ptr(), ctypes.addressof(batch.host_desc),
+                                  batch.dev_desc.data_ptr(), batch.n,
+                                  None if w_packed is None else w_packed.data_ptr(), dt, out.data_ptr(),
+                                  None if out_lo is None else out_lo.data_ptr(), ws.data_ptr(), ws.numel(), tile,
+                                  waves, _stream(batch.device)), "d8_accum_batched")
+    return out
+
+
+def accum_backward_batched(batch: Batch, dirs_packed, g_packed, *, tile=0, waves=0, out=None, ws=None):
+    dirs_packed = _dev_tensor(dirs_packed, torch.uint8, "dirs_packed")
+    g_packed = _dev_tensor(g_packed, torch.float32, "g_packed")
+    out = torch.empty(batch.total, dtype=torch.float32, device=batch.device) if out is None else out
+    nb = batch.workspace_bytes(tile)
+    ws = workspace(nb, batch.device) if ws is None else ws
+    _check(lib().d8_accum_backward_batched(dirs_packed.data_ptr(), ctypes.addressof(batch.host_desc),
+                                           batch.dev_desc.data_ptr(), batch.n, g_packed.data_ptr(), out.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), tile, waves, _stream(batch.device)),
+           "d8_accum_backward_batched")
+    return out

@@ -1,0 +1,366 @@
+// C ABI of the D8 library: argument checks, workspace layout, launch order.
+// Every entry point only enqueues on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "d8.h"
+#include "d8_internal.hpp"
+
+namespace d8 {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
+  p.ts = ts;
+  p.cap = 4 * ts - 4;
+  p.ntiles = ntiles;
+  p.nslots = ntiles * p.cap;
+  int r = 1;
+  while (((int64_t)1 << (r - 1)) <= p.nslots && r < kMaxRounds) ++r;
+  p.rounds = r;  // 2^(rounds-2) > nslots >= depth of the exit forest
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t o_hdr = take(kHdrBytes);
+  const size_t o_tab = take(sizeof(DemInfo) * (size_t)std::max(ndem, 1));
+  const size_t o_code = take((size_t)p.nslots);
+  const size_t o_rl = take((size_t)p.nslots * 2);
+  const size_t o_val = take((size_t)p.nslots * 8);
+  size_t o_buf[3], o_anc[2];
+  for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
+  for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
+  p.bytes = off;
+  if (base) {
+    char* b = static_cast<char*>(base);
+    p.hdr = reinterpret_cast<uint32_t*>(b + o_hdr);
+    p.demtab = reinterpret_cast<DemInfo*>(b + o_tab);
+    p.ex_code = reinterpret_cast<uint8_t*>(b + o_code);
+    p.rl = reinterpret_cast<uint16_t*>(b + o_rl);
+    p.ex_val = reinterpret_cast<uint64_t*>(b + o_val);
+    for (int i = 0; i < 3; ++i) p.buf[i] = reinterpret_cast<uint64_t*>(b + o_buf[i]);
+    for (int i = 0; i < 2; ++i) p.anc[i] = reinterpret_cast<int32_t*>(b + o_anc[i]);
+  }
+  return p.bytes;
+}
+
+static int pick_tile(int tile) {
+  if (tile == 0) return 64;
+  if (tile == 32 || tile == 64 || tile == 128) return tile;
+  return 0;
+}
+
+// Threads per tile workgroup: at most 64 cells per thread (source bit mask),
+// at most 16 for the backward pass (register double buffer).
+static int pick_threads(int ts, int waves, bool backward) {
+  int nt = waves > 0 ? 64 * waves : (ts == 32 ? 64 : (ts == 64 ? 256 : 1024));
+  const int cells = ts * ts;
+  const int maxc = backward ? 16 : 64;
+  while (nt < 1024 && (cells + nt - 1) / nt > maxc) nt *= 2;
+  if (nt > 1024) nt = 1024;
+  if (nt > cells) nt = std::max(64, cells);
+  return nt;
+}
+
+static bool shape_ok(int64_t rows, int64_t cols) {
+  return rows > 0 && cols > 0 && rows <= 0xFFFFFFFFll && cols <= 0xFFFFFFFFll &&
+         (uint64_t)rows * (uint64_t)cols <= 0xFFFFFFFFull;
+}
+
+static DemInfo single_dem(int64_t rows, int64_t cols, int ts) {
+  DemInfo d;
+  d.off = 0;
+  d.H = (int32_t)rows;
+  d.W = (int32_t)cols;
+  d.TY = (int32_t)((rows + ts - 1) / ts);
+  d.TX = (int32_t)((cols + ts - 1) / ts);
+  d.tile0 = 0;
+  return d;
+}
+
+static d8_status hip_status(hipError_t e) { return e == hipSuccess ? D8_OK : D8_EHIP; }
+
+}  // namespace d8
+
+using namespace d8;
+
+extern "C" {
+
+const char* d8_version(void) { return "d8-gfx950 0.1"; }
+
+const char* d8_strerror(d8_status s) {
+  switch (s) {
+    case D8_OK: return "ok";
+    case D8_EINVAL: return "invalid argument";
+    case D8_ENOMEM: return "workspace too small";
+    case D8_EHIP: return "HIP runtime error";
+    case D8_EBADDIR: return "invalid direction field (bad code, or a target off the grid or into NoData)";
+    case D8_ECYCLE: return "direction field contains a cycle";
+    case D8_EUNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown status";
+}
+
+d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream) {
+  if (!dem || !dirs || !shape_ok(rows, cols)) return D8_EINVAL;
+  DemTable tab{};
+  tab.n = 1;
+  tab.one = single_dem(rows, cols, kFlowdirsBlock);
+  const int64_t nb = (int64_t)tab.one.TY * tab.one.TX;
+  return hip_status(launch_flowdirs(dem, dirs, tab, nb, (hipStream_t)stream));
+}
+
+size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile) {
+  const int ts = pick_tile(tile);
+  if (!ts || !shape_ok(rows, cols)) return 0;
+  Plan p;
+  const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
+  return plan_layout(p, nt, ts, 1, nullptr);
+}
+
+static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size_t ws_bytes, int tile) {
+  const int ts = pick_tile(tile);
+  if (!ts || !shape_ok(rows, cols) || !ws) return D8_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
+  const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
+  if (plan_layout(p, nt, ts, 1, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, 1, ws);
+  p.tab.n = 1;
+  p.tab.dev = nullptr;
+  p.tab.one = single_dem(rows, cols, ts);
+  return D8_OK;
+}
+
+static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w, d8_dtype out_dtype, void* out,
+                             float* out_lo, int waves, hipStream_t s) {
+  hipError_t e = launch_zero_header(p.hdr, s);
+  if (e != hipSuccess) return D8_EHIP;
+  if (out_dtype == D8_U32) {
+    const int nt = pick_threads(p.ts, waves, false);
+    if ((e = launch_count_tiles(p, dirs, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_forward_resolve(p, false, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_count_tiles(p, dirs, true, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
+  } else {
+    if (p.ts > 64) return D8_EUNSUPPORTED;
+    const int nt = pick_threads(p.ts, waves, false);
+    if ((e = launch_weighted_tiles(p, dirs, w, false, nullptr, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_forward_resolve(p, true, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_weighted_tiles(p, dirs, w, true, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
+      return D8_EHIP;
+  }
+  return D8_OK;
+}
+
+static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g, float* gw, int waves,
+                              hipStream_t s) {
+  if (p.ts > 64) return D8_EUNSUPPORTED;
+  hipError_t e = launch_zero_header(p.hdr, s);
+  if (e != hipSuccess) return D8_EHIP;
+  const int nt = pick_threads(p.ts, waves, true);
+  if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+  if ((e = launch_backward_resolve(p, s)) != hipSuccess) return D8_EHIP;
+  if ((e = launch_backward_tiles(p, dirs, g, true, gw, nt, s)) != hipSuccess) return D8_EHIP;
+  return D8_OK;
+}
+
+d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights, d8_dtype out_dtype,
+                   void* out, float* out_lo, void* ws, size_t ws_bytes, int tile, void* stream) {
+  if (!dirs || !out) return D8_EINVAL;
+  if (out_dtype != D8_U32 && out_dtype != D8_F32) return D8_EINVAL;
+  if (out_dtype == D8_U32 && (weights || out_lo)) return D8_EINVAL;
+  Plan p;
+  d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
+  if (st != D8_OK) return st;
+  if (out_dtype == D8_F32 && p.ts > 64) return D8_EUNSUPPORTED;
+  return run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, (hipStream_t)stream);
+}
+
+d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
+                            float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream) {
+  if (!dirs || !grad_out || !grad_weights) return D8_EINVAL;
+  Plan p;
+  d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
+  if (st != D8_OK) return st;
+  if (p.ts > 64) return D8_EUNSUPPORTED;
+  return run_backward(p, dirs, grad_out, grad_weights, 0, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ batched --
+
+static bool batch_tiles(const d8_desc* hd, int32_t n, int ts, int64_t& ntiles) {
+  ntiles = 0;
+  if (!hd || n <= 0) return false;
+  for (int32_t i = 0; i < n; ++i) {
+    if (hd[i].rows <= 0 || hd[i].cols <= 0 || hd[i].offset < 0) return false;
+    if ((int64_t)hd[i].rows * hd[i].cols > 0x7FFFFFFFll) return false;
+    ntiles += ((int64_t)(hd[i].rows + ts - 1) / ts) * ((hd[i].cols + ts - 1) / ts);
+  }
+  return true;
+}
+
+size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile) {
+  const int ts = pick_tile(tile);
+  int64_t nt;
+  if (!ts || !batch_tiles(host_desc, n, ts, nt)) return 0;
+  int64_t ntf;
+  batch_tiles(host_desc, n, kFlowdirsBlock, ntf);
+  Plan p;
+  size_t b = plan_layout(p, nt, ts, n, nullptr);
+  return std::max(b, align256(kHdrBytes) + align256(sizeof(DemInfo) * (size_t)n));
+}
+
+static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int32_t n, void* ws, size_t ws_bytes,
+                              int ts, hipStream_t s) {
+  int64_t nt;
+  if (!ts || !dd || !ws || !batch_tiles(hd, n, ts, nt)) return D8_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
+  if (plan_layout(p, nt, ts, n, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, n, ws);
+  if (n == 1) {
+    p.tab.n = 1;
+    p.tab.dev = nullptr;
+    DemInfo d = single_dem(hd[0].rows, hd[0].cols, ts);
+    d.off = hd[0].offset;
+    p.tab.one = d;
+    return D8_OK;
+  }
+  p.tab.n = n;
+  p.tab.dev = p.demtab;
+  return hip_status(launch_build_demtab(dd, n, ts, p.demtab, s));
+}
+
+d8_status d8_flowdirs_batched(const float* dem_packed, const d8_desc* host_desc, const d8_desc* dev_desc, int32_t n,
+                              uint8_t* dirs_packed, void* ws, size_t ws_bytes, void* stream) {
+  if (!dem_packed || !dirs_packed) return D8_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Plan p;
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, kFlowdirsBlock, s);
+  if (st == D8_ENOMEM) {
+    // flowdirs needs only the header and the DEM table
+    if (ws_bytes < align256(kHdrBytes) + align256(sizeof(DemInfo) * (size_t)n)) return D8_ENOMEM;
+    int64_t nt;
+    batch_tiles(host_desc, n, kFlowdirsBlock, nt);
+    p = Plan();
+    p.hdr = static_cast<uint32_t*>(ws);
+    p.demtab = reinterpret_cast<DemInfo*>(static_cast<char*>(ws) + align256(kHdrBytes));
+    p.ntiles = nt;
+    if (n == 1) {
+      p.tab.n = 1;
+      p.tab.one = single_dem(host_desc[0].rows, host_desc[0].cols, kFlowdirsBlock);
+      p.tab.one.off = host_desc[0].offset;
+    } else {
+      p.tab.n = n;
+      p.tab.dev = p.demtab;
+      if (launch_build_demtab(dev_desc, n, kFlowdirsBlock, p.demtab, s) != hipSuccess) return D8_EHIP;
+    }
+  } else if (st != D8_OK) {
+    return st;
+  }
+  return hip_status(launch_flowdirs(dem_packed, dirs_packed, p.tab, p.ntiles, s));
+}
+
+d8_status d8_accum_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc, int32_t n,
+                           const float* w_packed, d8_dtype out_dtype, void* out_packed, float* out_lo_packed,
+                           void* ws, size_t ws_bytes, int tile, int waves, void* stream) {
+  if (!dirs_packed || !out_packed) return D8_EINVAL;
+  if (out_dtype != D8_U32 && out_dtype != D8_F32) return D8_EINVAL;
+  if (out_dtype == D8_U32 && (w_packed || out_lo_packed)) return D8_EINVAL;
+  if (waves < 0 || waves > 16) return D8_EINVAL;
+  const int ts = pick_tile(tile);
+  if (out_dtype == D8_F32 && ts > 64) return D8_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  Plan p;
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s);
+  if (st != D8_OK) return st;
+  return run_forward(p, dirs_packed, w_packed, out_dtype, out_packed, out_lo_packed, waves, s);
+}
+
+d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
+                                    int32_t n, const float* g_packed, float* gw_packed, void* ws, size_t ws_bytes,
+                                    int tile, int waves, void* stream) {
+  if (!dirs_packed || !g_packed || !gw_packed) return D8_EINVAL;
+  if (waves < 0 || waves > 16) return D8_EINVAL;
+  const int ts = pick_tile(tile);
+  if (ts > 64) return D8_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  Plan p;
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s);
+  if (st != D8_OK) return st;
+  return run_backward(p, dirs_packed, g_packed, gw_packed, waves, s);
+}
+
+d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
+                              int32_t n, const float* w_packed, float* out_scratch, float* g_scratch, void* ws,
+                              size_t ws_bytes, int* best_tile, int* best_waves, float* best_ms, void* stream) {
+  if (!best_tile || !best_waves) return D8_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return D8_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return D8_EHIP;
+  }
+  const int tiles[2] = {32, 64};
+  const int waves_opts[4] = {1, 2, 4, 8};
+  float best = 1e30f;
+  int bt = 0, bw = 0;
+  d8_status last = D8_OK;
+  for (int ti = 0; ti < 2; ++ti) {
+    for (int wi = 0; wi < 4; ++wi) {
+      const int t = tiles[ti], w = waves_opts[wi];
+      if (64 * w > t * t) continue;
+      float ms_best = 1e30f;
+      bool ok = true;
+      for (int rep = 0; rep < 3 && ok; ++rep) {
+        hipEventRecord(e0, s);
+        d8_status a = d8_accum_batched(dirs_packed, host_desc, dev_desc, n, w_packed, D8_F32, out_scratch, nullptr,
+                                       ws, ws_bytes, t, w, stream);
+        d8_status b = d8_accum_backward_batched(dirs_packed, host_desc, dev_desc, n, out_scratch, g_scratch, ws,
+                                                ws_bytes, t, w, stream);
+        hipEventRecord(e1, s);
+        if (a != D8_OK || b != D8_OK) {
+          ok = false;
+          last = a != D8_OK ? a : b;
+          break;
+        }
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          ok = false;
+          last = D8_EHIP;
+          break;
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_best = std::min(ms_best, ms);
+      }
+      if (ok && ms_best < best) {
+        best = ms_best;
+        bt = t;
+        bw = w;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!bt) return last == D8_OK ? D8_EUNSUPPORTED : last;
+  *best_tile = bt;
+  *best_waves = bw;
+  if (best_ms) *best_ms = best;
+  return D8_OK;
+}
+
+d8_status d8_device_status(const void* ws, void* stream, int32_t* status_out) {
+  if (!ws || !status_out) return D8_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return D8_EHIP;
+  uint32_t w = 0;
+  if (hipMemcpy(&w, ws, 4, hipMemcpyDeviceToHost) != hipSuccess) return D8_EHIP;
+  *status_out = (w & kStBadDir) ? D8_EBADDIR : ((w & kStCycle) ? D8_ECYCLE : D8_OK);
+  return D8_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Device-side helpers shared by the gfx950 kernels of the D8 library.
+//
+// Direction codes: 0 E, 1 NE, 2 N, 3 NW, 4 W, 5 SW, 6 S, 7 SE, 8 outlet,
+// 255 NoData (row 0 = north).  Code i drains to offset (ddr(i), ddc(i)); a
+// neighbour at offset i drains into the centre cell iff its code is (i+4)&7.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace d8 {
+
+constexpr uint8_t kNone = 8;
+constexpr uint8_t kNoData = 255;
+constexpr uint8_t kOutside = 254;  // halo cell beyond the DEM edge (LDS only)
+
+// Status word bits (workspace word 0).
+constexpr uint32_t kStBadDir = 1u;
+constexpr uint32_t kStCycle = 2u;
+
+// Offsets as small lookup functions (no memory traffic): rows then cols.
+__device__ __forceinline__ int ddr(int k) {
+  // k: 0 E 0, 1 NE -1, 2 N -1, 3 NW -1, 4 W 0, 5 SW +1, 6 S +1, 7 SE +1
+  return (k >= 1 && k <= 3) ? -1 : ((k >= 5) ? 1 : 0);
+}
+__device__ __forceinline__ int ddc(int k) {
+  // k: 0 E +1, 1 NE +1, 2 N 0, 3 NW -1, 4 W -1, 5 SW -1, 6 S 0, 7 SE +1
+  return (k == 0 || k == 1 || k == 7) ? 1 : ((k >= 3 && k <= 5) ? -1 : 0);
+}
+
+// ------------------------------------------------------------ tile geometry --
+// Perimeter slots of a tw x th tile (tw, th >= 1): top row, bottom row, left
+// column without corners, right column without corners.  These are the
+// paper's "edge cells" of a partition (Sec. 3), generalised from strips to
+// tiles.
+__device__ __forceinline__ int perim_count(int tw, int th) {
+  return th == 1 ? tw : (tw == 1 ? th : 2 * tw + 2 * (th - 2));
+}
+__device__ __forceinline__ bool on_perim(int r, int c, int tw, int th) {
+  return r == 0 || c == 0 || r == th - 1 || c == tw - 1;
+}
+__device__ __forceinline__ int perim_slot(int r, int c, int tw, int th) {
+  if (r == 0) return c;
+  if (r == th - 1) return tw + c;
+  if (c == 0) return 2 * tw + r - 1;
+  return 2 * tw + (th - 2) + r - 1;  // c == tw - 1
+}
+__device__ __forceinline__ void perim_cell(int j, int tw, int th, int& r, int& c) {
+  if (j < tw) { r = 0; c = j; return; }
+  if (j < 2 * tw) { r = th - 1; c = j - tw; return; }
+  if (j < 2 * tw + th - 2) { r = j - 2 * tw + 1; c = 0; return; }
+  r = j - 2 * tw - (th - 2) + 1;
+  c = tw - 1;
+}
+
+// One DEM of a (possibly single-element) batch, as the kernels see it.
+struct DemInfo {
+  int64_t off;    // element offset of cell (0,0) in the packed arrays
+  int32_t H, W;   // shape
+  int32_t TY, TX; // tile grid
+  int64_t tile0;  // first tile id of this DEM in the combined tile space
+};
+
+struct DemTable {
+  const DemInfo* dev;  // device table (n > 1), sorted by tile0
+  int32_t n;
+  DemInfo one;         // used when n == 1
+};
+
+__device__ __forceinline__ DemInfo dem_of_tile(const DemTable& t, int64_t tile) {
+  if (t.n == 1) return t.one;
+  int lo = 0, hi = t.n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t.dev[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return t.dev[lo];
+}
+
+// ----------------------------------------------------------- double-float --
+// A value is the unevaluated sum hi + lo of two float32 numbers.  Additions
+// use Knuth's TwoSum (an error-free transformation) followed by Dekker's
+// Fast2Sum renormalisation; no multiplications, so contraction cannot change
+// them.
+struct df {
+  float hi, lo;
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  e = b - (s - a);
+}
+__device__ __forceinline__ df df_add(df a, df b) {
+  float s, e;
+  two_sum(a.hi, b.hi, s, e);
+  e += a.lo + b.lo;
+  df r;
+  fast_two_sum(s, e, r.hi, r.lo);
+  return r;
+}
+__device__ __forceinline__ df df_from_double(double x) {
+  df r;
+  r.hi = (float)x;
+  r.lo = (float)(x - (double)r.hi);
+  return r;
+}
+__device__ __forceinline__ double df_to_double(df a) { return (double)a.hi + (double)a.lo; }
+
+__device__ __forceinline__ void set_status(uint32_t* st, uint32_t bit) {
+  __hip_atomic_fetch_or(st, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace d8

@@ -1,0 +1,62 @@
+// Host-side plan of one accumulation call and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "d8_dev.hpp"
+
+namespace d8 {
+
+// Workspace layout (all offsets 256-byte aligned):
+//   header   4096 B: [0] status word, [1] final-buffer index of the forward
+//            resolve, [2] of the backward resolve, [64..127] round flags
+//   demtab   DemInfo x ndem                (batched calls only)
+//   ex_code  uint8  x nslots   direction code of an exit slot, 0xFF otherwise
+//   rl       uint16 x nslots   receiver slot -> exit slot of its in-tile path
+//   ex_val   8 B    x nslots   exit partial value (forward) / receiver path
+//                              sum (backward)
+//   buf[3]   8 B    x nslots   resolve values
+//   anc[2]   int32  x nslots   resolve ancestor pointers
+// A slot is one perimeter cell of one tile: slot id = tile * cap + perimeter
+// index (see perim_slot).
+struct Plan {
+  int ts = 0;        // tile side
+  int cap = 0;       // perimeter slots per tile (4*ts - 4)
+  int64_t ntiles = 0;
+  int64_t nslots = 0;
+  int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
+  DemTable tab{};
+  uint32_t* hdr = nullptr;
+  DemInfo* demtab = nullptr;
+  uint8_t* ex_code = nullptr;
+  uint16_t* rl = nullptr;
+  uint64_t* ex_val = nullptr;
+  uint64_t* buf[3] = {nullptr, nullptr, nullptr};
+  int32_t* anc[2] = {nullptr, nullptr};
+  size_t bytes = 0;
+};
+
+constexpr size_t kHdrBytes = 4096;
+constexpr int kMaxRounds = 62;
+
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base);
+
+// Launchers (return hipError_t of the last launch).
+// Flow directions over 64x64-cell blocks (tab built with tile side 64).
+constexpr int kFlowdirsBlock = 64;
+hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s);
+hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, DemInfo* out, hipStream_t s);
+hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s);
+
+hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
+                              hipStream_t s);
+hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass,
+                                 float* out, float* out_lo, int nt, hipStream_t s);
+hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float* g, bool final_pass,
+                                 float* out, int nt, hipStream_t s);
+hipError_t launch_forward_resolve(const Plan& p, bool weighted, hipStream_t s);
+hipError_t launch_backward_resolve(const Plan& p, hipStream_t s);
+
+}  // namespace d8

@@ -1,0 +1,77 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1605_05773_amd as d8
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "d8.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(d8_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(d8.LIB_PATH):
+        pytest.skip("libd8.so not built")
+    L = d8.lib()
+    names = header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(d8.EXPORTED)
+
+
+def test_version_and_strerror():
+    L = d8.lib()
+    assert L.d8_version().startswith(b"d8-gfx950")
+    for s in range(7):
+        assert len(L.d8_strerror(s)) > 1
+
+
+def test_workspace_bytes_validation():
+    L = d8.lib()
+    assert L.d8_workspace_bytes(0, 10, 0) == 0
+    assert L.d8_workspace_bytes(10, -1, 0) == 0
+    assert L.d8_workspace_bytes(10, 10, 48) == 0
+    assert L.d8_workspace_bytes(1 << 17, 1 << 16, 0) == 0          # > 2^32 - 1 cells
+    a = L.d8_workspace_bytes(1000, 1000, 64)
+    b = L.d8_workspace_bytes(1000, 1000, 32)
+    assert 0 < a < b                                               # smaller tiles, more perimeter slots
+    assert L.d8_workspace_bytes(1, 1, 32) > 0
+
+
+def test_argument_errors_before_device_work():
+    L = d8.lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.d8_accum(None, 10, 10, None, d8.D8_U32, fake, None, fake, 1 << 30, 0, None) == d8.D8_EINVAL
+    assert L.d8_accum(fake, 10, 10, None, 7, fake, None, fake, 1 << 30, 0, None) == d8.D8_EINVAL
+    assert L.d8_accum(fake, 10, 10, fake, d8.D8_U32, fake, None, fake, 1 << 30, 0, None) == d8.D8_EINVAL
+    assert L.d8_accum(fake, 0, 10, None, d8.D8_U32, fake, None, fake, 1 << 30, 0, None) == d8.D8_EINVAL
+    # workspace pointer not 256-byte aligned
+    assert L.d8_accum(fake, 10, 10, None, d8.D8_U32, fake, None, ctypes.c_void_p(0x1010), 1 << 30, 0,
+                      None) == d8.D8_EINVAL
+    # workspace too small
+    assert L.d8_accum(fake, 100, 100, None, d8.D8_U32, fake, None, fake, 16, 0, None) == d8.D8_ENOMEM
+    # weighted with a 128 tile is not provided
+    assert L.d8_accum(fake, 100, 100, None, d8.D8_F32, fake, None, fake, 1 << 30, 128, None) == d8.D8_EUNSUPPORTED
+    assert L.d8_accum_backward(fake, 10, 10, None, fake, fake, 1 << 30, 0, None) == d8.D8_EINVAL
+    assert L.d8_flowdirs(None, 10, 10, fake, None) == d8.D8_EINVAL
+    assert L.d8_flowdirs(fake, 1 << 20, 1 << 13, fake, None) == d8.D8_EINVAL
+    assert L.d8_device_status(None, None, None) == d8.D8_EINVAL
+
+
+def test_batched_workspace_validation():
+    L = d8.lib()
+    descs = (d8.d8_desc * 2)(d8.d8_desc(0, 10, 20), d8.d8_desc(200, 30, 5))
+    assert L.d8_batched_workspace_bytes(ctypes.addressof(descs), 2, 64) > 0
+    bad = (d8.d8_desc * 1)(d8.d8_desc(0, 0, 20))
+    assert L.d8_batched_workspace_bytes(ctypes.addressof(bad), 1, 64) == 0
+    assert L.d8_batched_workspace_bytes(ctypes.addressof(descs), 0, 64) == 0
