@@ -1,0 +1,236 @@
+"""Benchmark: D8 up-slope area (flow accumulation) throughput on one MI355X.
+
+One step = one d8_accum call (tile pass with unknown inflows -> perimeter
+resolve -> final tile pass) over the resident direction field of the
+workload, unit weights, uint32 counts.  Prints ONE JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2a]
+
+Default workload: a 32768 x 32768 synthetic DEM (1.07 G cells; fBm sigma
+50 m, Hurst 0.7, tilt 0.01, eps-filled), the size the throughput target is
+stated for.  Inputs are generated on the host once (cached under
+$D8_CACHE), copied to HBM and converted to directions with d8_flowdirs
+before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcells/s D8 accumulation + % HBM roofline; fwd+bwd vs plain fwd Gcells/s"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per cell of each kernel phase (minimal model):
+#   count_tile_final : 1 B direction in + 4 B count out
+#   count_tile_emit  : 1 B direction in
+#   flowdirs         : 4 B elevation in + 1 B direction out
+ALG_BYTES_PER_CELL = {"count_tile_final": 5.0, "count_tile_emit": 1.0, "flowdirs": 5.0,
+                      "weighted_tile_final": 9.0, "weighted_tile_emit": 5.0,
+                      "backward_tile_final": 9.0, "backward_tile_emit": 5.0}
+OP_BYTES_PER_CELL = 5.0  # d8_accum counts: 1 B direction in + 4 B count out
+
+WORKLOADS = {
+    "c2a": "32768x32768 fBm DEM (sigma 50 m, Hurst 0.7, tilt 0.01, eps-filled 1e-3), unit weights, uint32 counts",
+    "c1": "8192x8192 fBm DEM (sigma 20 m) with ~5% NoData disks r=8..64, unit weights, uint32 counts",
+    "c2b": "16384x16384 walled serpentine DEM (one boustrophedon channel), unit weights, uint32 counts",
+    "c0": "512x512 fBm DEM (sigma 5 m), unit weights, uint32 counts",
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("d8_kernels.hip", "d8_dev.hpp"):
+        with open(os.path.join(ROOT, "paper_1605_05773_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(phase, workload, tile):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    rec = t.get(f"{phase}:{workload}:{tile}")
+    if not rec or rec.get("kernel_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(z_full, workload):
+    """The oracle (plain single-threaded C Kahn queue) on a bounded sample: the
+    top-left quarter of the same DEM, its own flow directions recomputed so the
+    crop is a valid field."""
+    import oracle
+
+    oracle.build()
+    H, W = z_full.shape
+    if H * W > (1 << 28):
+        h, w = H // 2, W // 2
+        sample = f"top-left {h}x{w} crop of the {workload} DEM (flow directions recomputed on the crop)"
+        z = np.ascontiguousarray(z_full[:h, :w])
+    else:
+        h, w = H, W
+        sample = f"the full {workload} DEM"
+        z = z_full
+    d = oracle.flowdirs(z)
+    t0 = time.perf_counter()
+    oracle.accum_u32(d)
+    dt = time.perf_counter() - t0
+    return {"value": round(h * w / dt / 1e9, 5), "unit": "Gcells/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "seconds": round(dt, 3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2a", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwdbwd", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one MI355X only (the path is single-GPU; "
+              "see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import demgen
+    import paper_1605_05773_amd as d8
+
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    z = demgen.config_dem(args.workload)
+    H, W = z.shape
+    log(f"workload {args.workload} {H}x{W} ready in {time.time() - t0:.1f}s")
+    dem = torch.from_numpy(np.ascontiguousarray(z)).to(dev)
+    dirs = d8.flowdirs(dem)
+    torch.cuda.synchronize()
+    del dem
+    out = torch.empty((H, W), dtype=torch.uint32, device=dev)
+    ws = d8.workspace(d8.workspace_bytes(H, W, args.tile), dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        d8.accum(dirs, tile=args.tile, out=out, ws=ws)
+    torch.cuda.synchronize()
+    st = d8.device_status(ws)
+    if st != d8.D8_OK:
+        raise SystemExit(f"device status {st} after warmup")
+    log(f"warmup done ({args.warmup} steps)")
+
+    # Timed region: exactly `steps` steps, synchronised on both sides.
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        d8.accum(dirs, tile=args.tile, out=out, ws=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    value = H * W / (ms_step * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Gcells/s (wall {wall:.2f}s)")
+
+    # Per-phase durations: the library records HIP events around each kernel
+    # phase on the same stream (a separate pass of the same steps).
+    d8.phase_timing(True)
+    for _ in range(args.steps):
+        d8.accum(dirs, tile=args.tile, out=out, ws=ws)
+    torch.cuda.synchronize()
+    phases = d8.phase_report()
+    d8.phase_timing(False)
+    phase_ms = {k: round(v[0] / v[1], 4) for k, v in phases.items()}
+    log(f"phases (ms/launch): {phase_ms}")
+    tile = args.tile or 64
+    dominant = max(phase_ms, key=phase_ms.get)
+    cells = H * W
+    if dominant in ALG_BYTES_PER_CELL:
+        alg = ALG_BYTES_PER_CELL[dominant] * cells
+        achieved = alg / (phase_ms[dominant] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dominant, args.workload, tile), "kernel": dominant,
+                "alg_bytes_per_launch": alg}
+    else:
+        # the resolve: latency-bound rounds over the perimeter graph; reported
+        # against HBM with the bytes of its slot arrays touched per round
+        roof = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                "traffic": measured_traffic(dominant, args.workload, tile), "kernel": dominant}
+    op_gbs = OP_BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9
+
+    extra = {"phase_ms": phase_ms, "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
+             "op_bytes_per_cell": OP_BYTES_PER_CELL, "wall_s": round(wall, 3)}
+
+    if not args.no_fwdbwd:
+        # Forward vs forward+backward of the differentiable weighted form on the
+        # 4096^2 workload (lognormal weights, positive upstream gradients).
+        zc3 = demgen.config_dem("c3")
+        d3 = d8.flowdirs(torch.from_numpy(zc3).to(dev))
+        w3 = torch.from_numpy(demgen.lognormal_f32(zc3.shape, 303)).to(dev)
+        g3 = torch.from_numpy(demgen.lognormal_f32(zc3.shape, 304)).to(dev)
+        o3 = torch.empty(zc3.shape, dtype=torch.float32, device=dev)
+        ws3 = torch.empty(d8.workspace_bytes(*zc3.shape, 0) + 256, dtype=torch.uint8, device=dev)
+        ws3 = ws3[(-ws3.data_ptr()) % 256:]
+        for _ in range(2):
+            d8.accum(d3, w3, out=o3, ws=ws3)
+            d8.accum_backward(d3, g3, ws=ws3)
+        torch.cuda.synchronize()
+        a0, a1, a2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a0.record(stream)
+        for _ in range(args.steps):
+            d8.accum(d3, w3, out=o3, ws=ws3)
+        a1.record(stream)
+        for _ in range(args.steps):
+            d8.accum(d3, w3, out=o3, ws=ws3)
+            d8.accum_backward(d3, g3, ws=ws3)
+        a2.record(stream)
+        torch.cuda.synchronize()
+        f_ms = a0.elapsed_time(a1) / args.steps
+        fb_ms = a1.elapsed_time(a2) / args.steps
+        n3 = zc3.size
+        extra["fwd_bwd"] = {"workload": "4096x4096 fBm DEM (sigma 5 m), lognormal(0,1) f32 weights",
+                            "fwd_gcells": round(n3 / f_ms / 1e6, 2), "fwd_bwd_gcells": round(n3 / fb_ms / 1e6, 2),
+                            "fwd_ms": round(f_ms, 4), "fwd_bwd_ms": round(fb_ms, 4),
+                            "ratio": round(f_ms / fb_ms, 4)}
+        log(f"fwd/bwd: {extra['fwd_bwd']}")
+        del d3, w3, g3, o3, ws3
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(z, args.workload)
+        log(f"cpu baseline: {cpu}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gcells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "rows": H, "cols": W,
+                   "tile": tile, "parallelism": "single-gpu"},
+        "roofline": roof, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

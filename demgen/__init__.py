@@ -53,7 +53,8 @@ def _lib():
             raise RuntimeError("demgen/_fill.so is not built; run __graft_entry__.build()")
         lib = ctypes.CDLL(_FILL_SO)
         lib.demgen_fill_eps.restype = ctypes.c_int
-        lib.demgen_fill_eps.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_float]
+        lib.demgen_fill_eps.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_float,
+                                        ctypes.c_int64]
         _fill_lib = lib
     return _fill_lib
 
@@ -61,7 +62,9 @@ def _lib():
 def fill_eps(z: np.ndarray, eps: float = 1e-3) -> np.ndarray:
     """Epsilon priority-flood fill, in place on a C-contiguous float32 array."""
     assert z.dtype == np.float32 and z.flags.c_contiguous and z.ndim == 2
-    rc = _lib().demgen_fill_eps(z.ctypes.data, z.shape[0], z.shape[1], ctypes.c_float(eps))
+    n = z.shape[0] * z.shape[1]
+    progress = (1 << 27) if n >= (1 << 28) else 0
+    rc = _lib().demgen_fill_eps(z.ctypes.data, z.shape[0], z.shape[1], ctypes.c_float(eps), progress)
     if rc != 0:
         raise MemoryError("fill: allocation failed")
     return z
@@ -131,10 +134,19 @@ def nodata_disks(z: np.ndarray, frac: float, seed: int, rmin: int = 8, rmax: int
     return disks
 
 
+def _say(msg):
+    import sys
+
+    print(f"[demgen] {msg}", file=sys.stderr, flush=True)
+
+
 def fbm_dem(rows: int, cols: int, sigma: float, seed: int, hurst: float = 0.7, slope: float = 0.01,
             eps: float = 1e-3, nodata_frac: float = 0.0, nodata_seed: int = 0) -> np.ndarray:
     """The full DEM recipe: fBm + tilt -> float32 -> NoData disks -> eps fill."""
+    big = rows * cols >= (1 << 26)
     z64 = fbm(rows, cols, hurst, sigma, seed)
+    if big:
+        _say(f"fbm {rows}x{cols} done")
     z = add_tilt_f32(z64, slope)
     del z64
     if nodata_frac > 0:

@@ -20,6 +20,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -29,50 +30,67 @@ static inline uint32_t fkey(float f) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-typedef struct { uint64_t* a; size_t n, cap; } heap_t;
+/* Radix heap (Ahuja, Mehlhorn, Orlin & Tarjan 1990) over 64-bit keys.  Valid
+ * because the flood is monotone: every key pushed after the first pop is
+ * larger than the last key popped.  Keys are unique (the cell index is in the
+ * low bits), so pops come out in exactly the order of a binary heap. */
+typedef struct { uint64_t* a; size_t n, cap; } vec_t;
+typedef struct { vec_t b[65]; uint64_t last; size_t n; } heap_t;
 
-static int heap_push(heap_t* h, uint64_t k) {
-  if (h->n == h->cap) {
-    size_t nc = h->cap ? h->cap * 2 : 1024;
-    uint64_t* na = (uint64_t*)realloc(h->a, nc * sizeof(uint64_t));
+static int vec_push(vec_t* v, uint64_t k) {
+  if (v->n == v->cap) {
+    size_t nc = v->cap ? v->cap * 2 : 256;
+    uint64_t* na = (uint64_t*)realloc(v->a, nc * sizeof(uint64_t));
     if (!na) return -1;
-    h->a = na; h->cap = nc;
+    v->a = na; v->cap = nc;
   }
-  size_t i = h->n++;
-  while (i > 0) {
-    size_t p = (i - 1) >> 1;
-    if (h->a[p] <= k) break;
-    h->a[i] = h->a[p];
-    i = p;
-  }
-  h->a[i] = k;
+  v->a[v->n++] = k;
   return 0;
 }
 
-static uint64_t heap_pop(heap_t* h) {
-  uint64_t top = h->a[0];
-  uint64_t last = h->a[--h->n];
-  size_t i = 0, n = h->n;
-  for (;;) {
-    size_t l = 2 * i + 1;
-    if (l >= n) break;
-    size_t m = (l + 1 < n && h->a[l + 1] < h->a[l]) ? l + 1 : l;
-    if (h->a[m] >= last) break;
-    h->a[i] = h->a[m];
-    i = m;
-  }
-  if (n) h->a[i] = last;
-  return top;
+static inline int bucket_of(uint64_t k, uint64_t last) {
+  uint64_t x = k ^ last;
+  return x ? 64 - __builtin_clzll(x) : 0;
 }
 
-/* Returns 0 on success, -1 on allocation failure. */
-int demgen_fill_eps(float* z, int64_t H, int64_t W, float eps) {
+static int heap_push(heap_t* h, uint64_t k) {
+  h->n++;
+  return vec_push(&h->b[bucket_of(k, h->last)], k);
+}
+
+static uint64_t heap_pop(heap_t* h) {
+  if (h->b[0].n == 0) {
+    int i = 1;
+    while (h->b[i].n == 0) ++i;
+    vec_t* v = &h->b[i];
+    uint64_t m = v->a[0];
+    for (size_t j = 1; j < v->n; ++j) if (v->a[j] < m) m = v->a[j];
+    h->last = m;
+    for (size_t j = 0; j < v->n; ++j) {
+      /* every key of bucket i lands in a lower bucket; cannot fail to grow
+         beyond what was already allocated in total, but check anyway */
+      if (vec_push(&h->b[bucket_of(v->a[j], m)], v->a[j])) return ~(uint64_t)0;
+    }
+    v->n = 0;
+  }
+  h->n--;
+  return h->b[0].a[--h->b[0].n];
+}
+
+static void heap_free(heap_t* h) {
+  for (int i = 0; i < 65; ++i) free(h->b[i].a);
+}
+
+/* Returns 0 on success, -1 on allocation failure.  If progress > 0, a line
+ * is written to stderr each time another `progress` cells have been settled. */
+int demgen_fill_eps(float* z, int64_t H, int64_t W, float eps, int64_t progress) {
   static const int DR[8] = {0, -1, -1, -1, 0, 1, 1, 1};
   static const int DC[8] = {1, 1, 0, -1, -1, -1, 0, 1};
   const int64_t N = H * W;
   uint8_t* seen = (uint8_t*)calloc((size_t)N, 1);
   uint32_t* pit = (uint32_t*)malloc((size_t)N * sizeof(uint32_t));
-  heap_t h = {0, 0, 0};
+  heap_t h;
+  memset(&h, 0, sizeof(h));
   if (!seen || !pit) { free(seen); free(pit); return -1; }
   for (int64_t r = 0; r < H; ++r) {
     for (int64_t c = 0; c < W; ++c) {
@@ -90,7 +108,12 @@ int demgen_fill_eps(float* z, int64_t H, int64_t W, float eps) {
   }
   {
     size_t ph = 0, pt = 0; /* FIFO head/tail into pit[] (each cell enters once) */
+    int64_t done = 0;
     while (ph < pt || h.n) {
+      if (progress > 0 && ++done % progress == 0) {
+        fprintf(stderr, "[demgen] fill: %lld of %lld cells settled\n", (long long)done, (long long)N);
+        fflush(stderr);
+      }
       uint32_t c;
       if (ph < pt) c = pit[ph++];
       else c = (uint32_t)(heap_pop(&h) & 0xffffffffu);
@@ -113,9 +136,9 @@ int demgen_fill_eps(float* z, int64_t H, int64_t W, float eps) {
       }
     }
   }
-  free(seen); free(pit); free(h.a);
+  free(seen); free(pit); heap_free(&h);
   return 0;
 oom:
-  free(seen); free(pit); free(h.a);
+  free(seen); free(pit); heap_free(&h);
   return -1;
 }

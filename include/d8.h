@@ -159,6 +159,16 @@ d8_status d8_device_status(const void* ws, void* stream, int32_t* status_out);
 /* Static text for a status code. */
 const char* d8_strerror(d8_status s);
 
+/* Phase timing, for measurement tools.  d8_phase_timing(1) clears the
+ * totals and makes every later call record a HIP event on its stream before
+ * and after each kernel phase; d8_phase_timing(0) stops recording.
+ * d8_phase_report synchronises the recorded events and returns, for phase
+ * index `phase` (0 .. D8_NPHASES-1), its name, the summed milliseconds and the
+ * number of timed calls.  Not thread-safe; host-side state only. */
+#define D8_NPHASES 10
+d8_status d8_phase_timing(int enable);
+d8_status d8_phase_report(int phase, const char** name, float* total_ms, int32_t* calls);
+
 /* Library version string. */
 const char* d8_version(void);
 

@@ -59,6 +59,8 @@ def lib():
             "d8_accum_backward_batched": ([P, P, P, I32, P, P, P, SZ, I32, I32, P], I32),
             "d8_autotune_batched": ([P, P, P, I32, P, P, P, P, SZ, P, P, P, P], I32),
             "d8_device_status": ([P, P, P], I32),
+            "d8_phase_timing": ([I32], I32),
+            "d8_phase_report": ([I32, P, P, P], I32),
             "d8_strerror": ([I32], ctypes.c_char_p),
             "d8_version": ([], ctypes.c_char_p),
         }
@@ -73,8 +75,9 @@ def lib():
 EXPORTED = (
     "d8_flowdirs", "d8_workspace_bytes", "d8_accum", "d8_accum_backward", "d8_batched_workspace_bytes",
     "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
-    "d8_device_status", "d8_strerror", "d8_version",
+    "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
 )
+NPHASES = 10
 
 
 def _check(st: int, what: str):
@@ -187,6 +190,24 @@ def device_status(ws: torch.Tensor | None = None, device=None) -> int:
     st = ctypes.c_int32(0)
     _check(lib().d8_device_status(ws.data_ptr(), _stream(ws.device), ctypes.byref(st)), "d8_device_status")
     return st.value
+
+
+def phase_timing(enable: bool):
+    """Start (clearing totals) or stop per-phase HIP-event timing in the library."""
+    _check(lib().d8_phase_timing(1 if enable else 0), "d8_phase_timing")
+
+
+def phase_report() -> dict:
+    """{phase name: (total ms, timed calls)} for every phase timed since phase_timing(True)."""
+    out = {}
+    for i in range(NPHASES):
+        name = ctypes.c_char_p()
+        ms = ctypes.c_float(0)
+        n = ctypes.c_int32(0)
+        _check(lib().d8_phase_report(i, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(n)), "d8_phase_report")
+        if n.value:
+            out[name.value.decode()] = (ms.value, n.value)
+    return out
 
 
 def _maybe_debug_check(ws, device):

@@ -51,7 +51,7 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
 }
 
 static int pick_tile(int tile) {
-  if (tile == 0) return 64;
+  if (tile == 0) return 32;
   if (tile == 32 || tile == 64 || tile == 128) return tile;
   return 0;
 }
@@ -61,7 +61,7 @@ static int pick_tile(int tile) {
 static int pick_threads(int ts, int waves, bool backward) {
   int nt = waves > 0 ? 64 * waves : (ts == 32 ? 64 : (ts == 64 ? 256 : 1024));
   const int cells = ts * ts;
-  const int maxc = backward ? 16 : 64;
+  const int maxc = backward ? 16 : 32;
   while (nt < 1024 && (cells + nt - 1) / nt > maxc) nt *= 2;
   if (nt > 1024) nt = 1024;
   if (nt > cells) nt = std::max(64, cells);
@@ -85,6 +85,71 @@ static DemInfo single_dem(int64_t rows, int64_t cols, int ts) {
 }
 
 static d8_status hip_status(hipError_t e) { return e == hipSuccess ? D8_OK : D8_EHIP; }
+
+// ------------------------------------------------------------ phase timing --
+enum Phase {
+  kPhFlowdirs = 0, kPhCountEmit, kPhCountResolve, kPhCountFinal, kPhWEmit, kPhWResolve, kPhWFinal,
+  kPhBEmit, kPhBResolve, kPhBFinal
+};
+static const char* kPhaseNames[D8_NPHASES] = {
+    "flowdirs", "count_tile_emit", "count_resolve", "count_tile_final", "weighted_tile_emit",
+    "weighted_resolve", "weighted_tile_final", "backward_tile_emit", "backward_resolve", "backward_tile_final"};
+
+struct PhaseRec {
+  int phase;
+  hipEvent_t a, b;
+};
+static bool g_timing = false;
+static std::vector<PhaseRec> g_pending;
+static std::vector<hipEvent_t> g_pool;
+static double g_ms[D8_NPHASES];
+static int g_calls[D8_NPHASES];
+
+static hipEvent_t ev_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct PhaseScope {
+  int ph;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseScope(int phase, hipStream_t st) : ph(phase), s(st) {
+    if (g_timing && (a = ev_get()) != nullptr && hipEventRecord(a, s) != hipSuccess) {
+      g_pool.push_back(a);
+      a = nullptr;
+    }
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = ev_get();
+    if (b && hipEventRecord(b, s) == hipSuccess) {
+      g_pending.push_back({ph, a, b});
+    } else {
+      g_pool.push_back(a);
+      if (b) g_pool.push_back(b);
+    }
+  }
+};
+
+static void drain_pending() {
+  for (auto& r : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      g_ms[r.phase] += ms;
+      g_calls[r.phase] += 1;
+    }
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_pending.clear();
+}
 
 }  // namespace d8
 
@@ -113,6 +178,7 @@ d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dir
   tab.n = 1;
   tab.one = single_dem(rows, cols, kFlowdirsBlock);
   const int64_t nb = (int64_t)tab.one.TY * tab.one.TX;
+  PhaseScope ps(kPhFlowdirs, (hipStream_t)stream);
   return hip_status(launch_flowdirs(dem, dirs, tab, nb, (hipStream_t)stream));
 }
 
@@ -143,16 +209,34 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
   if (e != hipSuccess) return D8_EHIP;
   if (out_dtype == D8_U32) {
     const int nt = pick_threads(p.ts, waves, false);
-    if ((e = launch_count_tiles(p, dirs, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
-    if ((e = launch_forward_resolve(p, false, s)) != hipSuccess) return D8_EHIP;
-    if ((e = launch_count_tiles(p, dirs, true, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
+    {
+      PhaseScope ps(kPhCountEmit, s);
+      if ((e = launch_count_tiles(p, dirs, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+    }
+    {
+      PhaseScope ps(kPhCountResolve, s);
+      if ((e = launch_forward_resolve(p, false, s)) != hipSuccess) return D8_EHIP;
+    }
+    {
+      PhaseScope ps(kPhCountFinal, s);
+      if ((e = launch_count_tiles(p, dirs, true, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
+    }
   } else {
     if (p.ts > 64) return D8_EUNSUPPORTED;
     const int nt = pick_threads(p.ts, waves, false);
-    if ((e = launch_weighted_tiles(p, dirs, w, false, nullptr, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
-    if ((e = launch_forward_resolve(p, true, s)) != hipSuccess) return D8_EHIP;
-    if ((e = launch_weighted_tiles(p, dirs, w, true, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
-      return D8_EHIP;
+    {
+      PhaseScope ps(kPhWEmit, s);
+      if ((e = launch_weighted_tiles(p, dirs, w, false, nullptr, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+    }
+    {
+      PhaseScope ps(kPhWResolve, s);
+      if ((e = launch_forward_resolve(p, true, s)) != hipSuccess) return D8_EHIP;
+    }
+    {
+      PhaseScope ps(kPhWFinal, s);
+      if ((e = launch_weighted_tiles(p, dirs, w, true, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
+        return D8_EHIP;
+    }
   }
   return D8_OK;
 }
@@ -163,9 +247,18 @@ static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g
   hipError_t e = launch_zero_header(p.hdr, s);
   if (e != hipSuccess) return D8_EHIP;
   const int nt = pick_threads(p.ts, waves, true);
-  if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
-  if ((e = launch_backward_resolve(p, s)) != hipSuccess) return D8_EHIP;
-  if ((e = launch_backward_tiles(p, dirs, g, true, gw, nt, s)) != hipSuccess) return D8_EHIP;
+  {
+    PhaseScope ps(kPhBEmit, s);
+    if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+  }
+  {
+    PhaseScope ps(kPhBResolve, s);
+    if ((e = launch_backward_resolve(p, s)) != hipSuccess) return D8_EHIP;
+  }
+  {
+    PhaseScope ps(kPhBFinal, s);
+    if ((e = launch_backward_tiles(p, dirs, g, true, gw, nt, s)) != hipSuccess) return D8_EHIP;
+  }
   return D8_OK;
 }
 
@@ -351,6 +444,27 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
   *best_tile = bt;
   *best_waves = bw;
   if (best_ms) *best_ms = best;
+  return D8_OK;
+}
+
+d8_status d8_phase_timing(int enable) {
+  drain_pending();
+  if (enable) {
+    for (int i = 0; i < D8_NPHASES; ++i) {
+      g_ms[i] = 0.0;
+      g_calls[i] = 0;
+    }
+  }
+  g_timing = enable != 0;
+  return D8_OK;
+}
+
+d8_status d8_phase_report(int phase, const char** name, float* total_ms, int32_t* calls) {
+  if (phase < 0 || phase >= D8_NPHASES) return D8_EINVAL;
+  drain_pending();
+  if (name) *name = kPhaseNames[phase];
+  if (total_ms) *total_ms = (float)g_ms[phase];
+  if (calls) *calls = g_calls[phase];
   return D8_OK;
 }
 

@@ -14,6 +14,8 @@
 //   tile pass, final  each tile recomputes its internal area with the resolved
 //                     inflow of each receiver added, i.e. adds the incoming
 //                     areas along the receivers' downstream paths (Alg. 7-8).
+#include <type_traits>
+
 #include "d8_internal.hpp"
 #include "d8.h"
 
@@ -140,18 +142,68 @@ __device__ __forceinline__ int64_t slot_of_cell(const DemInfo& dm, int64_t gy, i
   return ntile * cap + perim_slot((int)(gy - nty * ts), (int)(gx - ntx * ts), ntw, nth);
 }
 
-// Stage the tile's direction codes with a one-cell halo into LDS.
+// Stage the tile's direction codes with a one-cell halo into LDS.  When the
+// tile's rows are 4-byte aligned (full-width tile, width and offset multiples
+// of 4) the (TS+2) rows are fetched as 32-bit words, all loads of a thread
+// issued before any is consumed; the two halo columns are single bytes.
 template <int TS>
 __device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restrict__ dirs, const TileGeo& g) {
   constexpr int HS = TS + 2;
+  constexpr int WPR = TS / 4;     // 32-bit words per tile row
+  constexpr int NW = HS * WPR;    // rows y0-1 .. y0+TS
+  constexpr int MAXW = 9;         // >= ceil(NW / 64) for TS <= 32, ceil(NW / 256) for TS <= 64 ...
   const uint8_t* D = dirs + g.dm.off;
   const int64_t H = g.dm.H, W = g.dm.W;
-  for (int i = threadIdx.x; i < HS * HS; i += blockDim.x) {
-    const int lr = i / HS, lc = i - lr * HS;
-    const int64_t gy = g.y0 + lr - 1, gx = g.x0 + lc - 1;
-    uint8_t v = kOutside;
-    if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = D[gy * W + gx];
-    code[i] = v;
+  const int NT = blockDim.x, tid = threadIdx.x;
+  const bool vec = g.tw == TS && (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(D + g.x0) & 3) == 0) &&
+                   (NW + NT - 1) / NT <= MAXW && 2 * HS <= 2 * NT;
+  if (vec) {
+    uint32_t v[MAXW];
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+      const int i = tid + k * NT;
+      v[k] = 0xFEFEFEFEu;  // kOutside bytes
+      if (i < NW) {
+        const int lr = i / WPR, q = i - lr * WPR;
+        const int64_t gy = g.y0 + lr - 1;
+        if (gy >= 0 && gy < H) v[k] = *reinterpret_cast<const uint32_t*>(D + gy * W + g.x0 + 4 * q);
+      }
+    }
+    // halo columns x0-1 and x0+TS (2*HS bytes; at most two per thread)
+    uint8_t hb[2] = {kOutside, kOutside};
+    int hidx[2] = {-1, -1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int i = tid + k * NT;
+      if (i < 2 * HS) {
+        const int lr = i >> 1, side = i & 1;
+        const int64_t gy = g.y0 + lr - 1, gx = side ? g.x0 + TS : g.x0 - 1;
+        hidx[k] = lr * HS + (side ? HS - 1 : 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) hb[k] = D[gy * W + gx];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MAXW; ++k) {
+      const int i = tid + k * NT;
+      if (i < NW) {
+        const int lr = i / WPR, q = i - lr * WPR;
+        uint8_t* o = code + lr * HS + 1 + 4 * q;
+        o[0] = (uint8_t)v[k];
+        o[1] = (uint8_t)(v[k] >> 8);
+        o[2] = (uint8_t)(v[k] >> 16);
+        o[3] = (uint8_t)(v[k] >> 24);
+      }
+    }
+    if (hidx[0] >= 0) code[hidx[0]] = hb[0];
+    if (hidx[1] >= 0) code[hidx[1]] = hb[1];
+  } else {
+    for (int i = tid; i < HS * HS; i += NT) {
+      const int lr = i / HS, lc = i - lr * HS;
+      const int64_t gy = g.y0 + lr - 1, gx = g.x0 + lc - 1;
+      uint8_t v = kOutside;
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = D[gy * W + gx];
+      code[i] = v;
+    }
   }
 }
 
@@ -222,30 +274,55 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
 }
 
 // --------------------------------------------- counts: push-style tile walk --
-// LDS state per cell: val (bits 0..39) | pending inputs (40..47) | code (48..55).
-// A walker carries the final value v of its cell to the target with one
-// 64-bit LDS atomic that adds v and retires one pending input; the arrival
-// that retires the last input owns the target and continues downstream
-// (Alg. 2's tail recursion).  Integer sums: the result is order independent.
-template <int TS>
+// LDS state per cell, one word: value | pending inputs (4 bits) | in-tile
+// target (or kTgtExit: drains to another tile, kTgtEnd: outlet).  A walker
+// carries the final value v of its cell to the target with one LDS atomic that
+// adds v and retires one pending input; the arrival that retires the last
+// input owns the target and continues downstream (Alg. 2's tail recursion).
+// Integer sums: the result does not depend on the arrival order.
+template <typename Wd, int TS>
+struct CountWord {
+  static constexpr int kCells = TS * TS;
+  static constexpr int TB = (kCells <= 256 ? 9 : kCells <= 1024 ? 11 : kCells <= 4096 ? 13 : 15);
+  static constexpr int PB = 4;
+  static constexpr int VB = (int)sizeof(Wd) * 8 - TB - PB;
+  static constexpr Wd VMASK = (Wd(1) << VB) - 1;
+  static constexpr Wd PONE = Wd(1) << VB;
+  static constexpr int TSH = VB + PB;
+  static constexpr uint32_t kTgtExit = kCells;
+  static constexpr uint32_t kTgtEnd = kCells + 1;
+  __device__ static Wd make(uint32_t tgt, Wd val) { return val | (Wd(tgt) << TSH); }
+  __device__ static uint32_t tgt(Wd w) { return (uint32_t)(w >> TSH); }
+  __device__ static uint32_t pend(Wd w) { return (uint32_t)(w >> VB) & 15u; }
+  __device__ static Wd val(Wd w) { return w & VMASK; }
+};
+
+// Word type of the count walk: 32 bits while the largest tile-local value
+// (TS*TS, emit pass) fits, else 64 bits (final pass: values up to 2^32-1).
+template <int TS, bool FINAL>
+using CountW = typename std::conditional<(!FINAL && TS <= 64), uint32_t, unsigned long long>::type;
+
+template <int TS, bool FINAL>
 struct CountSmem {
-  uint64_t st[TS * TS];
+  CountW<TS, FINAL> st[TS * TS];
   uint8_t code[(TS + 2) * (TS + 2)];
 };
 
-template <int TS, bool FINAL>
-__global__ __launch_bounds__(1024) void k_tile_count(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
-                                                     int cap, uint8_t* __restrict__ ex_code,
-                                                     uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val,
-                                                     const uint64_t* __restrict__ F0,
-                                                     const uint64_t* __restrict__ F1,
-                                                     const uint64_t* __restrict__ F2, const uint32_t* __restrict__ hdr,
-                                                     uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
-  __shared__ CountSmem<TS> sm;
+template <int TS, int NT, bool FINAL>
+__global__ __launch_bounds__(NT) void k_tile_count(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
+                                                   int cap, uint8_t* __restrict__ ex_code,
+                                                   uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val,
+                                                   const uint64_t* __restrict__ F0, const uint64_t* __restrict__ F1,
+                                                   const uint64_t* __restrict__ F2, const uint32_t* __restrict__ hdr,
+                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+  using Wd = CountW<TS, FINAL>;
+  using CW = CountWord<Wd, TS>;
+  constexpr int CPT = TS * TS / NT;
+  static_assert(CPT * NT == TS * TS && CPT <= 32, "cells per thread");
+  __shared__ CountSmem<TS, FINAL> sm;
   constexpr int HS = TS + 2;
   const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
-  const int NT = blockDim.x, tid = threadIdx.x;
-  const int cpt = (TS * TS + NT - 1) / NT;
+  const int tid = threadIdx.x;
   load_codes<TS>(sm.code, dirs, g);
   __syncthreads();
 
@@ -254,75 +331,87 @@ __global__ __launch_bounds__(1024) void k_tile_count(const uint8_t* __restrict__
     const uint32_t fi = hdr[1];
     F = fi == 0 ? F0 : (fi == 1 ? F1 : F2);
   }
-  uint64_t src = 0;
-  for (int k = 0; k < cpt; ++k) {
+  // Phase A: per own cell, target and initial value.
+  uint32_t tg[CPT];
+  uint32_t valid = 0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NT;
-    if (c >= TS * TS) break;
     const int r = c / TS, col = c % TS;
-    uint64_t word = (uint64_t)kNoData << 48;
+    tg[k] = CW::kTgtEnd;
+    Wd word = CW::make(CW::kTgtEnd, 0);
     if (r < g.th && col < g.tw && sm.code[(r + 1) * HS + col + 1] != kNoData) {
+      valid |= 1u << k;
       const uint8_t e = eff_code<TS>(sm.code, r, col, g, status);
-      int pend;
-      uint32_t inm, ext;
-      inputs_of<TS>(sm.code, r, col, g, pend, inm, ext);
-      uint64_t v = 1;
-      if (FINAL && ext) v += gather_inflow<uint64_t>(F, ext, r, col, g, TS, cap);
-      word = v | ((uint64_t)pend << 40) | ((uint64_t)e << 48);
-      if (pend == 0) src |= 1ull << k;
+      if (e < 8) {
+        const int tr = r + ddr(e), tc = col + ddc(e);
+        tg[k] = (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) ? (uint32_t)(tr * TS + tc) : CW::kTgtExit;
+      }
+      Wd v = 1;
+      if (FINAL && on_perim(r, col, g.tw, g.th)) {
+        const uint32_t ext = ext_mask<TS>(sm.code, r, col, g);
+        if (ext) v += (Wd)gather_inflow<uint64_t>(F, ext, r, col, g, TS, cap);
+      }
+      word = CW::make(tg[k], v);
     }
     sm.st[c] = word;
   }
   __syncthreads();
+  // Phase B: count in-tile inputs (Alg. 1) by one atomic increment per edge.
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+    if (tg[k] < (uint32_t)(TS * TS)) atomicAdd(&sm.st[tg[k]], CW::PONE);
+  __syncthreads();
+  uint32_t src = 0;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * NT;
+    if ((valid >> k) & 1u) {
+      if (CW::pend(sm.st[c]) == 0) src |= 1u << k;
+    }
+  }
+  // Every wave must read its sources before any walker starts retiring
+  // inputs (a retired cell would otherwise look like a source).
+  __syncthreads();
 
   // Walk: one step per iteration for every lane that has work.
-  int cur = -1;
-  uint64_t v = 0;
-  uint32_t e = kNone;
+  uint32_t t = CW::kTgtEnd;
+  Wd v = 0;
   for (;;) {
-    if (cur < 0) {
+    if (t >= (uint32_t)(TS * TS)) {
       if (src == 0) break;
-      const int k = __builtin_ctzll(src);
+      const int k = __builtin_ctz(src);
       src &= src - 1;
-      cur = tid + k * NT;
-      const uint64_t w = sm.st[cur];
-      v = w & kValMask;
-      e = (uint32_t)(w >> 48) & 0xFF;
+      const Wd w = sm.st[tid + k * NT];
+      v = CW::val(w);
+      t = CW::tgt(w);
+      continue;
     }
-    int nxt = -1;
-    if (e < 8) {
-      const int r = cur / TS, col = cur % TS;
-      const int tr = r + ddr(e), tc = col + ddc(e);
-      if (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) {
-        const int t = tr * TS + tc;
-        const uint64_t old = atomicAdd((unsigned long long*)&sm.st[t], (unsigned long long)(v - kPendOne));
-        if (((old >> 40) & 0xFF) == 1) {
-          nxt = t;
-          v += old & kValMask;
-          e = (uint32_t)(old >> 48) & 0xFF;
-        }
-      }
+    const Wd old = atomicAdd(&sm.st[t], (Wd)(v - CW::PONE));
+    if (CW::pend(old) == 1) {
+      v += CW::val(old);
+      t = CW::tgt(old);
+    } else {
+      t = CW::kTgtEnd;
     }
-    cur = nxt;
   }
   __syncthreads();
 
   // Any cell still waiting for an input lies on or below a cycle.
   bool cyc = false;
-  for (int k = 0; k < cpt; ++k) {
-    const int c = tid + k * NT;
-    if (c >= TS * TS) break;
-    if ((sm.st[c] >> 40) & 0xFF) cyc = true;
-  }
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+    if (CW::pend(sm.st[tid + k * NT])) cyc = true;
   if (cyc) set_status(status, kStCycle);
 
   if (FINAL) {
     uint32_t* O = out + g.dm.off;
     const int64_t W = g.dm.W;
-    for (int k = 0; k < cpt; ++k) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
       const int c = tid + k * NT;
-      if (c >= TS * TS) break;
       const int r = c / TS, col = c % TS;
-      if (r < g.th && col < g.tw) O[(g.y0 + r) * W + g.x0 + col] = (uint32_t)(sm.st[c] & kValMask);
+      if (r < g.th && col < g.tw) O[(g.y0 + r) * W + g.x0 + col] = (uint32_t)CW::val(sm.st[c]);
     }
   } else {
     const int P = perim_count(g.tw, g.th);
@@ -332,30 +421,25 @@ __global__ __launch_bounds__(1024) void k_tile_count(const uint8_t* __restrict__
       if (j < P) {
         int r, col;
         perim_cell(j, g.tw, g.th, r, col);
-        const uint64_t w = sm.st[r * TS + col];
-        const uint32_t k = (uint32_t)(w >> 48) & 0xFF;
-        if (k < 8) {
-          const int tr = r + ddr(k), tc = col + ddc(k);
-          if (!(tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw)) {
-            ec = (uint8_t)k;
-            ex_val[sb + j] = w & kValMask;
-          }
+        const int c = r * TS + col;
+        const Wd w = sm.st[c];
+        if (CW::tgt(w) == CW::kTgtExit) {
+          ec = sm.code[(r + 1) * HS + col + 1];
+          ex_val[sb + j] = (uint64_t)CW::val(w);
         }
-        if (k != kNoData && ext_mask<TS>(sm.code, r, col, g)) {
+        if (sm.code[(r + 1) * HS + col + 1] != kNoData && ext_mask<TS>(sm.code, r, col, g)) {
           // Receiver: follow its in-tile path to the exit it leaves by.
-          int ur = r, uc = col, steps = 0;
+          int u = c, steps = 0;
           uint16_t link = 0xFFFF;
           for (;;) {
-            const uint32_t k2 = (uint32_t)(sm.st[ur * TS + uc] >> 48) & 0xFF;
-            if (k2 >= 8) break;
-            const int tr = ur + ddr(k2), tc = uc + ddc(k2);
-            if (tr < 0 || tr >= g.th || tc < 0 || tc >= g.tw) {
-              link = (uint16_t)perim_slot(ur, uc, g.tw, g.th);
+            const uint32_t tt = CW::tgt(sm.st[u]);
+            if (tt == CW::kTgtExit) {
+              link = (uint16_t)perim_slot(u / TS, u % TS, g.tw, g.th);
               break;
             }
-            ur = tr;
-            uc = tc;
-            if (++steps > g.tw * g.th) {
+            if (tt == CW::kTgtEnd) break;
+            u = (int)tt;
+            if (++steps > TS * TS) {
               set_status(status, kStCycle);
               break;
             }
@@ -836,7 +920,7 @@ __global__ void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int 
 static inline unsigned grid_for(int64_t n, int block) {
   int64_t g = (n + block - 1) / block;
   if (g < 1) g = 1;
-  if (g > 16384) g = 16384;
+  if (g > 2048) g = 2048;
   return (unsigned)g;
 }
 
@@ -856,27 +940,35 @@ hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab,
   return hipGetLastError();
 }
 
-template <int TS>
-static hipError_t count_ts(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, int nt, hipStream_t s) {
+template <int TS, int NT>
+static hipError_t count_ts(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
   uint32_t* st = p.hdr;
   const uint64_t* b0 = p.buf[0];
   const uint64_t* b1 = p.buf[1];
   const uint64_t* b2 = p.buf[2];
   if (fin)
-    hipLaunchKernelGGL((k_tile_count<TS, true>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, p.tab, p.ntiles,
+    hipLaunchKernelGGL((k_tile_count<TS, NT, true>), dim3((unsigned)p.ntiles), dim3(NT), 0, s, dirs, p.tab, p.ntiles,
                        p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
   else
-    hipLaunchKernelGGL((k_tile_count<TS, false>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, p.tab, p.ntiles,
-                       p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
+    hipLaunchKernelGGL((k_tile_count<TS, NT, false>), dim3((unsigned)p.ntiles), dim3(NT), 0, s, dirs, p.tab,
+                       p.ntiles, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
   return hipGetLastError();
 }
 
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
                               hipStream_t s) {
   switch (p.ts) {
-    case 32: return count_ts<32>(p, dirs, final_pass, out, nt, s);
-    case 64: return count_ts<64>(p, dirs, final_pass, out, nt, s);
-    case 128: return count_ts<128>(p, dirs, final_pass, out, nt, s);
+    case 32:
+      if (nt <= 64) return count_ts<32, 64>(p, dirs, final_pass, out, s);
+      if (nt <= 128) return count_ts<32, 128>(p, dirs, final_pass, out, s);
+      return count_ts<32, 256>(p, dirs, final_pass, out, s);
+    case 64:
+      if (nt <= 128) return count_ts<64, 128>(p, dirs, final_pass, out, s);
+      if (nt <= 256) return count_ts<64, 256>(p, dirs, final_pass, out, s);
+      return count_ts<64, 512>(p, dirs, final_pass, out, s);
+    case 128:
+      if (nt <= 512) return count_ts<128, 512>(p, dirs, final_pass, out, s);
+      return count_ts<128, 1024>(p, dirs, final_pass, out, s);
   }
   return hipErrorInvalidValue;
 }

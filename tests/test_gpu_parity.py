@@ -288,3 +288,39 @@ def test_batched_matches_single(tile, waves):
     for i, (ga, gg) in enumerate(zip(b.unpack(A), b.unpack(G))):
         assert_rel(to_np(ga), oracle.accum_f64(dirs[i], ws_[i]), 1e-6, f"batched fwd {i}")
         assert_rel(to_np(gg), oracle.backward_f64(dirs[i], gs_[i]), 1e-6, f"batched bwd {i}")
+
+
+# ------------------------------------------- every tile / waves configuration
+
+CONFIGS = [(32, 1), (32, 2), (32, 4), (64, 2), (64, 4), (64, 8), (128, 8), (128, 16)]
+
+
+@pytest.fixture(scope="module")
+def dem2k():
+    z = demgen.fbm_dem(2048, 1536, sigma=20.0, seed=1, nodata_frac=0.05, nodata_seed=101)
+    d = oracle.flowdirs(z)
+    return d, oracle.accum_u32(d)
+
+
+@pytest.mark.parametrize("tile,waves", CONFIGS)
+def test_counts_every_config_2k(dem2k, tile, waves):
+    d, ref = dem2k
+    H, W = d.shape
+    b = d8.Batch([(H, W)], dev())
+    out = d8.accum_batched(b, to_dev(d).reshape(-1), tile=tile, waves=waves)
+    got = to_np(out).reshape(H, W)
+    assert d8.device_status() == d8.D8_OK
+    np.testing.assert_array_equal(got, ref)
+
+
+@pytest.mark.parametrize("tile,waves", [(32, 1), (32, 2), (64, 4), (64, 8)])
+def test_weighted_and_backward_every_config_2k(dem2k, tile, waves):
+    d, _ = dem2k
+    H, W = d.shape
+    w = demgen.lognormal_f32(d.shape, 77)
+    b = d8.Batch([(H, W)], dev())
+    dd = to_dev(d).reshape(-1)
+    A = d8.accum_batched(b, dd, to_dev(w).reshape(-1), tile=tile, waves=waves)
+    assert_rel(to_np(A).reshape(H, W), oracle.accum_f64(d, w), 1e-6, "weighted")
+    G = d8.accum_backward_batched(b, dd, to_dev(w).reshape(-1), tile=tile, waves=waves)
+    assert_rel(to_np(G).reshape(H, W), oracle.backward_f64(d, w), 1e-6, "backward")
