@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (profiler calibration of byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one MI355X only (the path is single-GPU; "
@@ -161,7 +163,7 @@ def main():
     d8.phase_timing(False)
     phase_ms = {k: round(v[0] / v[1], 4) for k, v in phases.items()}
     log(f"phases (ms/launch): {phase_ms}")
-    tile = args.tile or 64
+    tile = args.tile or 64  # library default tile side
     dominant = max(phase_ms, key=phase_ms.get)
     cells = H * W
     if dominant in ALG_BYTES_PER_CELL:
@@ -214,6 +216,14 @@ def main():
                             "ratio": round(f_ms / fb_ms, 4)}
         log(f"fwd/bwd: {extra['fwd_bwd']}")
         del d3, w3, g3, o3, ws3
+
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy of 1 GiB done")
 
     cpu = None
     if not args.no_cpu_baseline:

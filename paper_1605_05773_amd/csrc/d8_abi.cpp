@@ -36,6 +36,7 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
   size_t o_buf[3], o_anc[2];
   for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
   for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
+  const size_t o_list = take((size_t)p.nslots * 4);
   p.bytes = off;
   if (base) {
     char* b = static_cast<char*>(base);
@@ -46,12 +47,13 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
     p.ex_val = reinterpret_cast<uint64_t*>(b + o_val);
     for (int i = 0; i < 3; ++i) p.buf[i] = reinterpret_cast<uint64_t*>(b + o_buf[i]);
     for (int i = 0; i < 2; ++i) p.anc[i] = reinterpret_cast<int32_t*>(b + o_anc[i]);
+    p.list = reinterpret_cast<int32_t*>(b + o_list);
   }
   return p.bytes;
 }
 
 static int pick_tile(int tile) {
-  if (tile == 0) return 32;
+  if (tile == 0) return 64;
   if (tile == 32 || tile == 64 || tile == 128) return tile;
   return 0;
 }
@@ -61,7 +63,7 @@ static int pick_tile(int tile) {
 static int pick_threads(int ts, int waves, bool backward) {
   int nt = waves > 0 ? 64 * waves : (ts == 32 ? 64 : (ts == 64 ? 256 : 1024));
   const int cells = ts * ts;
-  const int maxc = backward ? 16 : 32;
+  const int maxc = backward ? 16 : 64;
   while (nt < 1024 && (cells + nt - 1) / nt > maxc) nt *= 2;
   if (nt > 1024) nt = 1024;
   if (nt > cells) nt = std::max(64, cells);
@@ -73,15 +75,38 @@ static bool shape_ok(int64_t rows, int64_t cols) {
          (uint64_t)rows * (uint64_t)cols <= 0xFFFFFFFFull;
 }
 
-static DemInfo single_dem(int64_t rows, int64_t cols, int ts) {
+static DemInfo single_dem(int64_t rows, int64_t cols, int ts, int waves = 0) {
   DemInfo d;
+  int bw, bh;
+  count_block_dims(ts, waves, bw, bh);
   d.off = 0;
   d.H = (int32_t)rows;
   d.W = (int32_t)cols;
   d.TY = (int32_t)((rows + ts - 1) / ts);
   d.TX = (int32_t)((cols + ts - 1) / ts);
   d.tile0 = 0;
+  d.BY = (int32_t)((rows + bh - 1) / bh);
+  d.BX = (int32_t)((cols + bw - 1) / bw);
+  d.blk0 = 0;
+  d.SBY = (int32_t)((rows + kSuper - 1) / kSuper);
+  d.SBX = (int32_t)((cols + kSuper - 1) / kSuper);
+  d.sb0 = 0;
   return d;
+}
+
+static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves) {
+  count_block_dims(p.ts, waves, p.bw, p.bh);
+  p.nblocks = 0;
+  p.nsb = 0;
+  if (hd) {
+    for (int32_t i = 0; i < n; ++i) {
+      p.nblocks += ((int64_t)(hd[i].rows + p.bh - 1) / p.bh) * ((hd[i].cols + p.bw - 1) / p.bw);
+      p.nsb += ((int64_t)(hd[i].rows + kSuper - 1) / kSuper) * ((hd[i].cols + kSuper - 1) / kSuper);
+    }
+  } else {
+    p.nblocks = ((rows + p.bh - 1) / p.bh) * ((cols + p.bw - 1) / p.bw);
+    p.nsb = ((rows + kSuper - 1) / kSuper) * ((cols + kSuper - 1) / kSuper);
+  }
 }
 
 static d8_status hip_status(hipError_t e) { return e == hipSuccess ? D8_OK : D8_EHIP; }
@@ -197,6 +222,7 @@ static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
   if (plan_layout(p, nt, ts, 1, nullptr) > ws_bytes) return D8_ENOMEM;
   plan_layout(p, nt, ts, 1, ws);
+  set_blocks(p, nullptr, 1, rows, cols, 0);
   p.tab.n = 1;
   p.tab.dev = nullptr;
   p.tab.one = single_dem(rows, cols, ts);
@@ -309,23 +335,24 @@ size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile)
 }
 
 static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int32_t n, void* ws, size_t ws_bytes,
-                              int ts, hipStream_t s) {
+                              int ts, hipStream_t s, int waves = 0) {
   int64_t nt;
   if (!ts || !dd || !ws || !batch_tiles(hd, n, ts, nt)) return D8_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
   if (plan_layout(p, nt, ts, n, nullptr) > ws_bytes) return D8_ENOMEM;
   plan_layout(p, nt, ts, n, ws);
+  set_blocks(p, hd, n, 0, 0, waves);
   if (n == 1) {
     p.tab.n = 1;
     p.tab.dev = nullptr;
-    DemInfo d = single_dem(hd[0].rows, hd[0].cols, ts);
+    DemInfo d = single_dem(hd[0].rows, hd[0].cols, ts, waves);
     d.off = hd[0].offset;
     p.tab.one = d;
     return D8_OK;
   }
   p.tab.n = n;
   p.tab.dev = p.demtab;
-  return hip_status(launch_build_demtab(dd, n, ts, p.demtab, s));
+  return hip_status(launch_build_demtab(dd, n, ts, p.bw, p.bh, p.demtab, s));
 }
 
 d8_status d8_flowdirs_batched(const float* dem_packed, const d8_desc* host_desc, const d8_desc* dev_desc, int32_t n,
@@ -350,7 +377,8 @@ d8_status d8_flowdirs_batched(const float* dem_packed, const d8_desc* host_desc,
     } else {
       p.tab.n = n;
       p.tab.dev = p.demtab;
-      if (launch_build_demtab(dev_desc, n, kFlowdirsBlock, p.demtab, s) != hipSuccess) return D8_EHIP;
+      if (launch_build_demtab(dev_desc, n, kFlowdirsBlock, kFlowdirsBlock, kFlowdirsBlock, p.demtab, s) != hipSuccess)
+        return D8_EHIP;
     }
   } else if (st != D8_OK) {
     return st;
@@ -369,7 +397,7 @@ d8_status d8_accum_batched(const uint8_t* dirs_packed, const d8_desc* host_desc,
   if (out_dtype == D8_F32 && ts > 64) return D8_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan p;
-  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s);
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves);
   if (st != D8_OK) return st;
   return run_forward(p, dirs_packed, w_packed, out_dtype, out_packed, out_lo_packed, waves, s);
 }

@@ -18,6 +18,10 @@ constexpr uint8_t kOutside = 254;  // halo cell beyond the DEM edge (LDS only)
 constexpr uint32_t kStBadDir = 1u;
 constexpr uint32_t kStCycle = 2u;
 
+// Offsets from packed 2-bit tables (value + 1), branch-free; k in 0..7.
+__device__ __forceinline__ int ddr_t(uint32_t k) { return (int)((0xA901u >> (2 * k)) & 3u) - 1; }
+__device__ __forceinline__ int ddc_t(uint32_t k) { return (int)((0x901Au >> (2 * k)) & 3u) - 1; }
+
 // Offsets as small lookup functions (no memory traffic): rows then cols.
 __device__ __forceinline__ int ddr(int k) {
   // k: 0 E 0, 1 NE -1, 2 N -1, 3 NW -1, 4 W 0, 5 SW +1, 6 S +1, 7 SE +1
@@ -55,17 +59,45 @@ __device__ __forceinline__ void perim_cell(int j, int tw, int th, int& r, int& c
 
 // One DEM of a (possibly single-element) batch, as the kernels see it.
 struct DemInfo {
-  int64_t off;    // element offset of cell (0,0) in the packed arrays
-  int32_t H, W;   // shape
-  int32_t TY, TX; // tile grid
-  int64_t tile0;  // first tile id of this DEM in the combined tile space
+  int64_t off;      // element offset of cell (0,0) in the packed arrays
+  int32_t H, W;     // shape
+  int32_t TY, TX;   // tile grid
+  int64_t tile0;    // first tile id of this DEM in the combined tile space
+  int32_t BY, BX;   // grid of workgroup blocks (a block holds whole tiles)
+  int64_t blk0;     // first block id of this DEM in the combined block space
+  int32_t SBY, SBX; // grid of super-blocks (kSuper x kSuper cells of whole tiles)
+  int64_t sb0;      // first super-block id of this DEM
 };
+
+// Side, in cells, of the super-blocks in which the tile-exit forest is
+// resolved locally before the global resolve.
+constexpr int kSuper = 256;
 
 struct DemTable {
   const DemInfo* dev;  // device table (n > 1), sorted by tile0
   int32_t n;
   DemInfo one;         // used when n == 1
 };
+
+__device__ __forceinline__ DemInfo dem_of_block(const DemTable& t, int64_t blk) {
+  if (t.n == 1) return t.one;
+  int lo = 0, hi = t.n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t.dev[mid].blk0 <= blk) lo = mid; else hi = mid - 1;
+  }
+  return t.dev[lo];
+}
+
+__device__ __forceinline__ DemInfo dem_of_sb(const DemTable& t, int64_t sb) {
+  if (t.n == 1) return t.one;
+  int lo = 0, hi = t.n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (t.dev[mid].sb0 <= sb) lo = mid; else hi = mid - 1;
+  }
+  return t.dev[lo];
+}
 
 __device__ __forceinline__ DemInfo dem_of_tile(const DemTable& t, int64_t tile) {
   if (t.n == 1) return t.one;

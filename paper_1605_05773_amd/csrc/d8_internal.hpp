@@ -18,7 +18,9 @@ namespace d8 {
 //   ex_val   8 B    x nslots   exit partial value (forward) / receiver path
 //                              sum (backward)
 //   buf[3]   8 B    x nslots   resolve values
-//   anc[2]   int32  x nslots   resolve ancestor pointers
+//   anc[2]   int32  x nslots   resolve ancestor pointers (anc[1] first holds
+//                              each tile exit's super-block root)
+//   list     int32  x nslots   compacted super-block exit slots
 // A slot is one perimeter cell of one tile: slot id = tile * cap + perimeter
 // index (see perim_slot).
 struct Plan {
@@ -27,6 +29,10 @@ struct Plan {
   int64_t ntiles = 0;
   int64_t nslots = 0;
   int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
+  int bw = 0, bh = 0;  // workgroup block of the count passes (whole tiles)
+  int64_t nblocks = 0;
+  int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
+  int32_t* list = nullptr;  // compacted super-block exit slots
   DemTable tab{};
   uint32_t* hdr = nullptr;
   DemInfo* demtab = nullptr;
@@ -47,7 +53,9 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base);
 // Flow directions over 64x64-cell blocks (tab built with tile side 64).
 constexpr int kFlowdirsBlock = 64;
 hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s);
-hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, DemInfo* out, hipStream_t s);
+hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, int bh, DemInfo* out,
+                               hipStream_t s);
+void count_block_dims(int ts, int waves, int& bw, int& bh);
 hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s);
 
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,

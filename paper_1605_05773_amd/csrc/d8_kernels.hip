@@ -21,6 +21,11 @@
 
 namespace d8 {
 
+// Optional per-phase cycle stamps for measurement builds (no-op here).
+#ifndef D8_STAMP
+#define D8_STAMP(i)
+#endif
+
 constexpr uint64_t kValMask = (1ull << 40) - 1;
 constexpr uint64_t kPendOne = 1ull << 40;
 
@@ -142,21 +147,24 @@ __device__ __forceinline__ int64_t slot_of_cell(const DemInfo& dm, int64_t gy, i
   return ntile * cap + perim_slot((int)(gy - nty * ts), (int)(gx - ntx * ts), ntw, nth);
 }
 
-// Stage the tile's direction codes with a one-cell halo into LDS.  When the
-// tile's rows are 4-byte aligned (full-width tile, width and offset multiples
-// of 4) the (TS+2) rows are fetched as 32-bit words, all loads of a thread
-// issued before any is consumed; the two halo columns are single bytes.
-template <int TS>
-__device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restrict__ dirs, const TileGeo& g) {
-  constexpr int HS = TS + 2;
-  constexpr int WPR = TS / 4;     // 32-bit words per tile row
-  constexpr int NW = HS * WPR;    // rows y0-1 .. y0+TS
-  constexpr int MAXW = 9;         // >= ceil(NW / 64) for TS <= 32, ceil(NW / 256) for TS <= 64 ...
-  const uint8_t* D = dirs + g.dm.off;
-  const int64_t H = g.dm.H, W = g.dm.W;
+// Stage a BW x BH block of direction codes with a one-cell halo into LDS
+// (row stride BW + 2).  When the block's rows are 4-byte aligned (full-width
+// block, width and offset multiples of 4) the BH + 2 rows are fetched as
+// 32-bit words, all loads of a thread issued before any is consumed; the two
+// halo columns are single bytes.
+template <int BW, int BH>
+__device__ __forceinline__ void load_halo(uint8_t* code, const uint8_t* __restrict__ dirs, const DemInfo& dm,
+                                          int64_t y0, int64_t x0, int bw) {
+  constexpr int HS = BW + 2;
+  constexpr int HR = BH + 2;
+  constexpr int WPR = BW / 4;     // 32-bit words per block row
+  constexpr int NW = HR * WPR;    // rows y0-1 .. y0+BH
+  constexpr int MAXW = 9;
+  const uint8_t* D = dirs + dm.off;
+  const int64_t H = dm.H, W = dm.W;
   const int NT = blockDim.x, tid = threadIdx.x;
-  const bool vec = g.tw == TS && (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(D + g.x0) & 3) == 0) &&
-                   (NW + NT - 1) / NT <= MAXW && 2 * HS <= 2 * NT;
+  const bool vec = bw == BW && (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(D + x0) & 3) == 0) &&
+                   (NW + NT - 1) / NT <= MAXW && HR <= NT;
   if (vec) {
     uint32_t v[MAXW];
 #pragma unroll
@@ -165,19 +173,19 @@ __device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restr
       v[k] = 0xFEFEFEFEu;  // kOutside bytes
       if (i < NW) {
         const int lr = i / WPR, q = i - lr * WPR;
-        const int64_t gy = g.y0 + lr - 1;
-        if (gy >= 0 && gy < H) v[k] = *reinterpret_cast<const uint32_t*>(D + gy * W + g.x0 + 4 * q);
+        const int64_t gy = y0 + lr - 1;
+        if (gy >= 0 && gy < H) v[k] = *reinterpret_cast<const uint32_t*>(D + gy * W + x0 + 4 * q);
       }
     }
-    // halo columns x0-1 and x0+TS (2*HS bytes; at most two per thread)
+    // halo columns x0-1 and x0+BW (2*HR bytes; at most two per thread)
     uint8_t hb[2] = {kOutside, kOutside};
     int hidx[2] = {-1, -1};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const int i = tid + k * NT;
-      if (i < 2 * HS) {
+      if (i < 2 * HR) {
         const int lr = i >> 1, side = i & 1;
-        const int64_t gy = g.y0 + lr - 1, gx = side ? g.x0 + TS : g.x0 - 1;
+        const int64_t gy = y0 + lr - 1, gx = side ? x0 + BW : x0 - 1;
         hidx[k] = lr * HS + (side ? HS - 1 : 0);
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) hb[k] = D[gy * W + gx];
       }
@@ -197,14 +205,19 @@ __device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restr
     if (hidx[0] >= 0) code[hidx[0]] = hb[0];
     if (hidx[1] >= 0) code[hidx[1]] = hb[1];
   } else {
-    for (int i = tid; i < HS * HS; i += NT) {
+    for (int i = tid; i < HS * HR; i += NT) {
       const int lr = i / HS, lc = i - lr * HS;
-      const int64_t gy = g.y0 + lr - 1, gx = g.x0 + lc - 1;
+      const int64_t gy = y0 + lr - 1, gx = x0 + lc - 1;
       uint8_t v = kOutside;
       if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = D[gy * W + gx];
       code[i] = v;
     }
   }
+}
+
+template <int TS>
+__device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restrict__ dirs, const TileGeo& g) {
+  load_halo<TS, TS>(code, dirs, g.dm, g.y0, g.x0, g.tw);
 }
 
 // Validated code of in-tile cell (r, c): 0..7 (drains to a valid cell), 8
@@ -228,34 +241,47 @@ __device__ __forceinline__ uint8_t eff_code(const uint8_t* code, int r, int c, c
   return k;
 }
 
-// In-tile input count and mask, and the mask of inputs from outside the tile.
+// Masks of the inputs of in-tile cell (r, c): bit i set if the neighbour at
+// offset i drains into the cell; split into inputs inside the tile and inputs
+// from outside it (receivers).  Branch-free.
+template <int TS>
+__device__ __forceinline__ uint32_t input_mask(const uint8_t* code, int r, int c) {
+  constexpr int HS = TS + 2;
+  const uint8_t* p = code + (r + 1) * HS + c + 1;
+  uint32_t m = 0;
+  m |= (uint32_t)(p[1] == 4) << 0;        // E neighbour drains W
+  m |= (uint32_t)(p[1 - HS] == 5) << 1;   // NE drains SW
+  m |= (uint32_t)(p[-HS] == 6) << 2;      // N drains S
+  m |= (uint32_t)(p[-1 - HS] == 7) << 3;  // NW drains SE
+  m |= (uint32_t)(p[-1] == 0) << 4;       // W drains E
+  m |= (uint32_t)(p[HS - 1] == 1) << 5;   // SW drains NE
+  m |= (uint32_t)(p[HS] == 2) << 6;       // S drains N
+  m |= (uint32_t)(p[HS + 1] == 3) << 7;   // SE drains NW
+  return m;
+}
+
+// Directions i whose neighbour (r + ddr(i), c + ddc(i)) lies outside the tile.
+__device__ __forceinline__ uint32_t outside_dirs(int r, int c, int tw, int th) {
+  const uint32_t n = r == 0 ? 0x0Eu : 0u;        // NE N NW
+  const uint32_t s = r == th - 1 ? 0xE0u : 0u;   // SW S SE
+  const uint32_t w = c == 0 ? 0x38u : 0u;        // NW W SW
+  const uint32_t e = c == tw - 1 ? 0x83u : 0u;   // E NE SE
+  return n | s | w | e;
+}
+
 template <int TS>
 __device__ __forceinline__ void inputs_of(const uint8_t* code, int r, int c, const TileGeo& g, int& pend,
                                           uint32_t& inm, uint32_t& ext) {
-  constexpr int HS = TS + 2;
-  pend = 0;
-  inm = 0;
-  ext = 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int nr = r + ddr(i), nc = c + ddc(i);
-    if (code[(nr + 1) * HS + nc + 1] == ((i + 4) & 7)) {
-      if (nr >= 0 && nr < g.th && nc >= 0 && nc < g.tw) {
-        ++pend;
-        inm |= 1u << i;
-      } else {
-        ext |= 1u << i;
-      }
-    }
-  }
+  const uint32_t m = input_mask<TS>(code, r, c);
+  const uint32_t out = outside_dirs(r, c, g.tw, g.th);
+  inm = m & ~out;
+  ext = m & out;
+  pend = __builtin_popcount(inm);
 }
 
 template <int TS>
 __device__ __forceinline__ uint32_t ext_mask(const uint8_t* code, int r, int c, const TileGeo& g) {
-  int p;
-  uint32_t m, e;
-  inputs_of<TS>(code, r, c, g, p, m, e);
-  return e;
+  return input_mask<TS>(code, r, c) & outside_dirs(r, c, g.tw, g.th);
 }
 
 // Sum of the resolved areas of the exits (in other tiles) that drain into
@@ -273,176 +299,216 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
   return x;
 }
 
-// --------------------------------------------- counts: push-style tile walk --
-// LDS state per cell, one word: value | pending inputs (4 bits) | in-tile
-// target (or kTgtExit: drains to another tile, kTgtEnd: outlet).  A walker
-// carries the final value v of its cell to the target with one LDS atomic that
-// adds v and retires one pending input; the arrival that retires the last
-// input owns the target and continues downstream (Alg. 2's tail recursion).
-// Integer sums: the result does not depend on the arrival order.
-template <typename Wd, int TS>
-struct CountWord {
-  static constexpr int kCells = TS * TS;
-  static constexpr int TB = (kCells <= 256 ? 9 : kCells <= 1024 ? 11 : kCells <= 4096 ? 13 : 15);
-  static constexpr int PB = 4;
-  static constexpr int VB = (int)sizeof(Wd) * 8 - TB - PB;
-  static constexpr Wd VMASK = (Wd(1) << VB) - 1;
-  static constexpr Wd PONE = Wd(1) << VB;
-  static constexpr int TSH = VB + PB;
-  static constexpr uint32_t kTgtExit = kCells;
-  static constexpr uint32_t kTgtEnd = kCells + 1;
-  __device__ static Wd make(uint32_t tgt, Wd val) { return val | (Wd(tgt) << TSH); }
-  __device__ static uint32_t tgt(Wd w) { return (uint32_t)(w >> TSH); }
-  __device__ static uint32_t pend(Wd w) { return (uint32_t)(w >> VB) & 15u; }
-  __device__ static Wd val(Wd w) { return w & VMASK; }
+// --------------------------------------------------- counts: tile doubling --
+// A workgroup owns a BW x BH block of cells made of whole TS x TS tiles (the
+// tiles of a block are independent).  Inside a tile the up-slope area with
+// unknown inflows (Alg. 2) is A = (I - P)^-1 w, evaluated as
+// (I + P)(I + P^2)(I + P^4)... w: in round j every cell whose 2^j-th in-tile
+// ancestor exists adds its current value to that ancestor, then jumps its
+// ancestor pointer to the ancestor's ancestor.  After ceil(log2(depth)) rounds
+// every cell holds its tile-local area.  Control flow is uniform and cells
+// close to their tile root drop out early; integer sums make the result
+// independent of the order of the atomic additions.
+constexpr uint16_t kNoAnc = 0xFFFF;
+constexpr int kDblCpt = 16;  // cells per thread
+
+// Per cell: value, and a link word (low 16 bits: the exact 2^j-th in-tile
+// ancestor or kNoAnc; high 16 bits: the ancestor at distance
+// min(2^j, distance to the tile root), i.e. the root once the exact
+// ancestor has run out).
+template <int BW, int BH>
+struct DblSmem {
+  uint32_t val[BW * BH];
+  uint32_t link[BW * BH];
+  uint8_t code[(BW + 2) * (BH + 2)];
 };
 
-// Word type of the count walk: 32 bits while the largest tile-local value
-// (TS*TS, emit pass) fits, else 64 bits (final pass: values up to 2^32-1).
-template <int TS, bool FINAL>
-using CountW = typename std::conditional<(!FINAL && TS <= 64), uint32_t, unsigned long long>::type;
-
-template <int TS, bool FINAL>
-struct CountSmem {
-  CountW<TS, FINAL> st[TS * TS];
-  uint8_t code[(TS + 2) * (TS + 2)];
+struct BlockGeo {
+  DemInfo dm;
+  int64_t y0, x0;       // block origin
+  int64_t ty0, tx0;     // global tile coordinates of the block's first tile
+  int bw, bh;           // block extent clipped to the DEM
 };
 
-template <int TS, int NT, bool FINAL>
-__global__ __launch_bounds__(NT) void k_tile_count(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
-                                                   int cap, uint8_t* __restrict__ ex_code,
-                                                   uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val,
-                                                   const uint64_t* __restrict__ F0, const uint64_t* __restrict__ F1,
-                                                   const uint64_t* __restrict__ F2, const uint32_t* __restrict__ hdr,
-                                                   uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
-  using Wd = CountW<TS, FINAL>;
-  using CW = CountWord<Wd, TS>;
-  constexpr int CPT = TS * TS / NT;
-  static_assert(CPT * NT == TS * TS && CPT <= 32, "cells per thread");
-  __shared__ CountSmem<TS, FINAL> sm;
-  constexpr int HS = TS + 2;
-  const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
+template <int BW, int BH, int TS>
+__device__ __forceinline__ BlockGeo block_geo(const DemTable& tab, int64_t blk) {
+  BlockGeo b;
+  b.dm = dem_of_block(tab, blk);
+  const int64_t lb = blk - b.dm.blk0;
+  const int64_t by = lb / b.dm.BX, bx = lb - by * b.dm.BX;
+  b.y0 = by * BH;
+  b.x0 = bx * BW;
+  b.ty0 = by * (BH / TS);
+  b.tx0 = bx * (BW / TS);
+  b.bh = (int)min((int64_t)BH, (int64_t)b.dm.H - b.y0);
+  b.bw = (int)min((int64_t)BW, (int64_t)b.dm.W - b.x0);
+  return b;
+}
+
+template <int BW, int BH, int TS, bool FINAL>
+__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
+    const uint8_t* __restrict__ dirs, DemTable tab, int64_t nblocks, int cap, uint8_t* __restrict__ ex_code,
+    uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val, const uint64_t* __restrict__ F0,
+    const uint64_t* __restrict__ F1, const uint64_t* __restrict__ F2, const uint32_t* __restrict__ hdr,
+    uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+  constexpr int NC = BW * BH;
+  constexpr int NT = NC / kDblCpt;
+  constexpr int HS = BW + 2;
+  constexpr int TPX = BW / TS, TPY = BH / TS;  // tiles per block row / column
+  static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
+  __shared__ DblSmem<BW, BH> sm;
+  const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
   const int tid = threadIdx.x;
-  load_codes<TS>(sm.code, dirs, g);
+  D8_STAMP(0);
+  load_halo<BW, BH>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
   __syncthreads();
+  D8_STAMP(1);
 
-  const uint64_t* F = nullptr;
+  // Setup: in-tile target (ancestor at distance 1) and initial value.
+  uint16_t a[kDblCpt];
+#pragma unroll
+  for (int k = 0; k < kDblCpt; ++k) {
+    const int c = tid + k * NT;
+    const int r = c / BW, col = c % BW;
+    const uint32_t code = sm.code[(r + 1) * HS + col + 1];
+    const bool ok = r < g.bh && col < g.bw && code != kNoData;
+    const uint32_t d = code & 7u;
+    const int dr = ddr_t(d), dc = ddc_t(d);
+    const int ta = r / TS, tb = col / TS;
+    const int th = min(TS, g.bh - ta * TS), tw = min(TS, g.bw - tb * TS);
+    const int tr = r - ta * TS + dr, tc = col - tb * TS + dc;
+    const bool drains = ok && code < 8u;
+    const bool inside = drains && tr >= 0 && tr < th && tc >= 0 && tc < tw;
+    const uint8_t tcode = sm.code[(r + 1 + dr) * HS + col + 1 + dc];
+    if (ok && (code > 8u || (drains && tcode == kNoData) ||
+               (drains && !inside &&
+                (g.y0 + r + dr < 0 || g.y0 + r + dr >= g.dm.H || g.x0 + col + dc < 0 || g.x0 + col + dc >= g.dm.W)))) {
+      set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
+    }
+    a[k] = (inside && tcode != kNoData) ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
+    sm.val[c] = ok ? 1u : 0u;
+    sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
+  }
+  __syncthreads();
   if (FINAL) {
-    const uint32_t fi = hdr[1];
-    F = fi == 0 ? F0 : (fi == 1 ? F1 : F2);
-  }
-  // Phase A: per own cell, target and initial value.
-  uint32_t tg[CPT];
-  uint32_t valid = 0;
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const int c = tid + k * NT;
-    const int r = c / TS, col = c % TS;
-    tg[k] = CW::kTgtEnd;
-    Wd word = CW::make(CW::kTgtEnd, 0);
-    if (r < g.th && col < g.tw && sm.code[(r + 1) * HS + col + 1] != kNoData) {
-      valid |= 1u << k;
-      const uint8_t e = eff_code<TS>(sm.code, r, col, g, status);
-      if (e < 8) {
-        const int tr = r + ddr(e), tc = col + ddc(e);
-        tg[k] = (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) ? (uint32_t)(tr * TS + tc) : CW::kTgtExit;
+    // Inflow of every receiver: the resolved areas of the exits of other
+    // tiles that drain into it (the paper's incoming area, Alg. 7).
+    const uint64_t* F;
+    {
+      const uint32_t fi = hdr[1];
+      F = fi == 0 ? F0 : (fi == 1 ? F1 : F2);
+    }
+    for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
+      const int tl = idx / cap, j = idx - tl * cap;
+      const int ta = tl / TPX, tb = tl - ta * TPX;
+      const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
+      if (th <= 0 || tw <= 0) continue;
+      const int thc = min(TS, th), twc = min(TS, tw);
+      if (j >= perim_count(twc, thc)) continue;
+      int lr, lc;
+      perim_cell(j, twc, thc, lr, lc);
+      const int r = ta * TS + lr, col = tb * TS + lc;
+      if (sm.code[(r + 1) * HS + col + 1] == kNoData) continue;
+      const uint32_t ext = input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc);
+      if (ext) {
+        TileGeo tg;
+        tg.dm = g.dm;
+        tg.y0 = g.y0 + ta * TS;
+        tg.x0 = g.x0 + tb * TS;
+        tg.th = thc;
+        tg.tw = twc;
+        sm.val[r * BW + col] += (uint32_t)gather_inflow<uint64_t>(F, ext, lr, lc, tg, TS, cap);
       }
-      Wd v = 1;
-      if (FINAL && on_perim(r, col, g.tw, g.th)) {
-        const uint32_t ext = ext_mask<TS>(sm.code, r, col, g);
-        if (ext) v += (Wd)gather_inflow<uint64_t>(F, ext, r, col, g, TS, cap);
+    }
+    __syncthreads();
+  }
+  D8_STAMP(2);
+  D8_STAMP(3);
+
+  // Doubling rounds.  Reads of a round (own value, ancestor's link word) all
+  // happen before the barrier, updates after it.  The saturating pointer
+  // becomes the ancestor's saturating pointer when the exact one runs out.
+  const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
+  for (int round = 0;; ++round) {
+    uint32_t v[kDblCpt];
+    uint32_t nl[kDblCpt];
+#pragma unroll
+    for (int k = 0; k < kDblCpt; ++k) {
+      if (a[k] != kNoAnc) {
+        v[k] = sm.val[tid + k * NT];
+        nl[k] = sm.link[a[k]];
       }
-      word = CW::make(tg[k], v);
     }
-    sm.st[c] = word;
-  }
-  __syncthreads();
-  // Phase B: count in-tile inputs (Alg. 1) by one atomic increment per edge.
+    __syncthreads();
+    bool more = false;
 #pragma unroll
-  for (int k = 0; k < CPT; ++k)
-    if (tg[k] < (uint32_t)(TS * TS)) atomicAdd(&sm.st[tg[k]], CW::PONE);
-  __syncthreads();
-  uint32_t src = 0;
-#pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const int c = tid + k * NT;
-    if ((valid >> k) & 1u) {
-      if (CW::pend(sm.st[c]) == 0) src |= 1u << k;
+    for (int k = 0; k < kDblCpt; ++k) {
+      if (a[k] != kNoAnc) {
+        atomicAdd(&sm.val[a[k]], v[k]);
+        const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
+        const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
+        a[k] = na;
+        sm.link[tid + k * NT] = (uint32_t)na | (root << 16);
+        more |= na != kNoAnc;
+      }
     }
-  }
-  // Every wave must read its sources before any walker starts retiring
-  // inputs (a retired cell would otherwise look like a source).
-  __syncthreads();
-
-  // Walk: one step per iteration for every lane that has work.
-  uint32_t t = CW::kTgtEnd;
-  Wd v = 0;
-  for (;;) {
-    if (t >= (uint32_t)(TS * TS)) {
-      if (src == 0) break;
-      const int k = __builtin_ctz(src);
-      src &= src - 1;
-      const Wd w = sm.st[tid + k * NT];
-      v = CW::val(w);
-      t = CW::tgt(w);
-      continue;
-    }
-    const Wd old = atomicAdd(&sm.st[t], (Wd)(v - CW::PONE));
-    if (CW::pend(old) == 1) {
-      v += CW::val(old);
-      t = CW::tgt(old);
-    } else {
-      t = CW::kTgtEnd;
+    if (!__syncthreads_or(more)) break;
+    if (round >= max_rounds) {
+      set_status(status, kStCycle);  // a cycle never runs out of ancestors
+      break;
     }
   }
   __syncthreads();
-
-  // Any cell still waiting for an input lies on or below a cycle.
-  bool cyc = false;
-#pragma unroll
-  for (int k = 0; k < CPT; ++k)
-    if (CW::pend(sm.st[tid + k * NT])) cyc = true;
-  if (cyc) set_status(status, kStCycle);
+  D8_STAMP(4);
 
   if (FINAL) {
     uint32_t* O = out + g.dm.off;
     const int64_t W = g.dm.W;
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
+    for (int k = 0; k < kDblCpt; ++k) {
       const int c = tid + k * NT;
-      const int r = c / TS, col = c % TS;
-      if (r < g.th && col < g.tw) O[(g.y0 + r) * W + g.x0 + col] = (uint32_t)CW::val(sm.st[c]);
+      const int r = c / BW, col = c % BW;
+      if (r < g.bh && col < g.bw) O[(g.y0 + r) * W + g.x0 + col] = sm.val[c];
     }
   } else {
-    const int P = perim_count(g.tw, g.th);
-    const int64_t sb = g.tile * cap;
-    for (int j = tid; j < cap; j += NT) {
+    // Perimeter records of every tile of the block: exit values, and for each
+    // receiver the exit its in-tile path leaves by.
+    for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
+      const int tl = idx / cap, j = idx - tl * cap;
+      const int ta = tl / TPX, tb = tl - ta * TPX;
+      const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
+      if (th <= 0 || tw <= 0) continue;  // tile beyond the DEM edge
+      const int thc = min(TS, th), twc = min(TS, tw);
+      const int64_t sb = (g.dm.tile0 + (g.ty0 + ta) * g.dm.TX + g.tx0 + tb) * cap;
       uint8_t ec = 0xFF;
-      if (j < P) {
-        int r, col;
-        perim_cell(j, g.tw, g.th, r, col);
-        const int c = r * TS + col;
-        const Wd w = sm.st[c];
-        if (CW::tgt(w) == CW::kTgtExit) {
-          ec = sm.code[(r + 1) * HS + col + 1];
-          ex_val[sb + j] = (uint64_t)CW::val(w);
+      if (j < perim_count(twc, thc)) {
+        int lr, lc;
+        perim_cell(j, twc, thc, lr, lc);
+        const int r = ta * TS + lr, col = tb * TS + lc;
+        const uint32_t code = sm.code[(r + 1) * HS + col + 1];
+        if (code < 8u) {
+          const int tr = lr + ddr_t(code), tc = lc + ddc_t(code);
+          if (!(tr >= 0 && tr < thc && tc >= 0 && tc < twc)) {
+            const int64_t gy = g.y0 + r + ddr_t(code), gx = g.x0 + col + ddc_t(code);
+            if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
+                sm.code[(r + 1 + ddr_t(code)) * HS + col + 1 + ddc_t(code)] != kNoData) {
+              ec = (uint8_t)code;
+              ex_val[sb + j] = (uint64_t)sm.val[r * BW + col];
+            }
+          }
         }
-        if (sm.code[(r + 1) * HS + col + 1] != kNoData && ext_mask<TS>(sm.code, r, col, g)) {
-          // Receiver: follow its in-tile path to the exit it leaves by.
-          int u = c, steps = 0;
+        if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
+          // Receiver: the root of its in-tile path is the exit it leaves by,
+          // unless the path ends at an outlet.
+          const int root = (int)(sm.link[r * BW + col] >> 16);
+          const int R = root / BW, C = root % BW;
+          const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
           uint16_t link = 0xFFFF;
-          for (;;) {
-            const uint32_t tt = CW::tgt(sm.st[u]);
-            if (tt == CW::kTgtExit) {
-              link = (uint16_t)perim_slot(u / TS, u % TS, g.tw, g.th);
-              break;
-            }
-            if (tt == CW::kTgtEnd) break;
-            u = (int)tt;
-            if (++steps > TS * TS) {
-              set_status(status, kStCycle);
-              break;
-            }
+          if (k2 < 8u) {
+            const int64_t gy = g.y0 + R + ddr_t(k2), gx = g.x0 + C + ddc_t(k2);
+            if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
+                sm.code[(R + 1 + ddr_t(k2)) * HS + C + 1 + ddc_t(k2)] != kNoData)
+              link = (uint16_t)perim_slot(R - ta * TS, C - tb * TS, twc, thc);
           }
           rl[sb + j] = link;
         }
@@ -450,6 +516,7 @@ __global__ __launch_bounds__(NT) void k_tile_count(const uint8_t* __restrict__ d
       ex_code[sb + j] = ec;
     }
   }
+  D8_STAMP(5);
 }
 
 // ------------------------------------------ weighted: gather-style tile walk --
@@ -833,6 +900,272 @@ __global__ void k_fres_round(int j, int64_t nslots, const uint8_t* __restrict__ 
   if (more) hdr[64 + j + 1] = 1;
 }
 
+// ------------------------------------------------ super-block group pass --
+// The tile exits of a kSuper x kSuper super-block form a forest whose edges
+// stay inside the super-block except at its own exits.  One workgroup
+// resolves that forest in LDS (the same doubling as the tile pass, now over
+// exit nodes), so the global resolve only sees super-block exits.  The
+// downward pass redoes it with the resolved inflows of the super-block's
+// receivers added and writes the full area of every tile exit.
+template <typename LV>
+struct GroupSmem;
+
+template <int TS, typename LV>
+struct GroupDims {
+  static constexpr int G = kSuper / TS;
+  static constexpr int CAP = 4 * TS - 4;
+  static constexpr int NN = G * G * CAP;
+  static constexpr int NT = 512;
+  static constexpr int NPT = (NN + NT - 1) / NT;
+};
+
+__device__ __forceinline__ void ladd(uint32_t* p, uint32_t v) { atomicAdd(p, v); }
+__device__ __forceinline__ void ladd(double* p, double v) { atomicAdd(p, v); }
+
+template <int TS, typename LV, typename V, bool DOWN>
+__global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const uint8_t* __restrict__ ex_code,
+                                               const uint16_t* __restrict__ rl, V* __restrict__ ex_val,
+                                               V* __restrict__ l2out, int32_t* __restrict__ sbroot,
+                                               int32_t* __restrict__ tgt_exit, int32_t* __restrict__ list,
+                                               const V* __restrict__ F0, const V* __restrict__ F1,
+                                               const V* __restrict__ F2, uint32_t* __restrict__ hdr,
+                                               uint32_t* __restrict__ status) {
+  using D = GroupDims<TS, LV>;
+  constexpr int G = D::G, CAP = D::CAP, NN = D::NN, NT = D::NT, NPT = D::NPT;
+  __shared__ LV val[NN];
+  __shared__ uint32_t link[NN];
+  __shared__ uint8_t flag[NN];  // bit 0: an exit of its tile; bit 1: leaves the super-block
+  const int tid = threadIdx.x;
+  const int64_t sbid = xcd_tile(blockIdx.x, nsb);
+  const DemInfo dm = dem_of_sb(tab, sbid);
+  const int64_t lsb = sbid - dm.sb0;
+  const int64_t sby = lsb / dm.SBX, sbx = lsb - sby * dm.SBX;
+  const int64_t ty0 = sby * G, tx0 = sbx * G;
+  const int64_t y0 = sby * kSuper, x0 = sbx * kSuper;
+  const int sbh = (int)min((int64_t)kSuper, (int64_t)dm.H - y0);
+  const int sbw = (int)min((int64_t)kSuper, (int64_t)dm.W - x0);
+
+  uint16_t a[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = tid + k * NT;
+    a[k] = kNoAnc;
+    if (n >= NN) continue;
+    const int tl = n / CAP, j = n - tl * CAP;
+    const int ta = tl / G, tb = tl - ta * G;
+    const int64_t ty = ty0 + ta, tx = tx0 + tb;
+    const bool tile_ok = ty < dm.TY && tx < dm.TX;
+    const int64_t s = (dm.tile0 + ty * dm.TX + tx) * CAP + j;
+    const uint8_t ec = tile_ok ? ex_code[s] : (uint8_t)0xFF;
+    LV v = 0;
+    uint8_t f = 0;
+    if (ec < 8) {
+      f = 1;
+      v = (LV)ex_val[s];
+      const int th = (int)min((int64_t)TS, (int64_t)dm.H - ty * TS);
+      const int tw = (int)min((int64_t)TS, (int64_t)dm.W - tx * TS);
+      int r, c;
+      perim_cell(j, tw, th, r, c);
+      const int64_t gy = ty * TS + r + ddr_t(ec), gx = tx * TS + c + ddc_t(ec);
+      // the target receiver's tile and its slot there
+      const int64_t tty = gy / TS, ttx = gx / TS;
+      const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
+      const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
+      const int64_t tbase = (dm.tile0 + tty * dm.TX + ttx) * CAP;
+      const uint16_t lk = rl[tbase + perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth)];
+      if (gy >= y0 && gy < y0 + sbh && gx >= x0 && gx < x0 + sbw) {
+        if (lk != 0xFFFF) a[k] = (uint16_t)(((tty - ty0) * G + (ttx - tx0)) * CAP + lk);
+      } else {
+        f |= 2;
+        // super-block exit: remember the tile exit its target receiver leads
+        // to; the global resolve turns it into a parent via that exit's
+        // super-block root
+        if (!DOWN) tgt_exit[s] = lk == 0xFFFF ? -1 : (int32_t)(tbase + lk);
+      }
+    }
+    val[n] = v;
+    link[n] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)n) << 16);
+    flag[n] = f;
+  }
+  __syncthreads();
+  if (DOWN) {
+    // Resolved inflow of every receiver on the super-block's border, added at
+    // the tile exit its in-tile path leaves by.
+    const V* F = F0;  // resolved super-block exit values
+    const int P = perim_count(sbw, sbh);
+    for (int i = tid; i < P; i += NT) {
+      int r, c;
+      perim_cell(i, sbw, sbh, r, c);
+      const int64_t gy = y0 + r, gx = x0 + c;
+      const uint32_t out = outside_dirs(r, c, sbw, sbh);
+      V x = 0;
+      for (int d = 0; d < 8; ++d) {
+        if (!(out & (1u << d))) continue;
+        const int64_t ny = gy + ddr_t(d), nx = gx + ddc_t(d);
+        if (ny < 0 || ny >= dm.H || nx < 0 || nx >= dm.W) continue;
+        const int64_t ns = slot_of_cell(dm, ny, nx, TS, CAP);
+        const uint8_t ecn = ex_code[ns];
+        if (ecn < 8 && ny + ddr_t(ecn) == gy && nx + ddc_t(ecn) == gx) x += F[ns];
+      }
+      if (x != (V)0) {
+        const int64_t tty = gy / TS, ttx = gx / TS;
+        const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
+        const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
+        const int64_t tbase = (dm.tile0 + tty * dm.TX + ttx) * CAP;
+        const uint16_t lk = rl[tbase + perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth)];
+        if (lk != 0xFFFF) ladd(&val[((tty - ty0) * G + (ttx - tx0)) * CAP + lk], (LV)x);
+      }
+    }
+    __syncthreads();
+  }
+
+  const int max_rounds = 2 + 31 - __builtin_clz((unsigned)NN);
+  for (int round = 0;; ++round) {
+    LV v[NPT];
+    uint32_t nl[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      if (a[k] != kNoAnc) {
+        v[k] = val[tid + k * NT];
+        nl[k] = link[a[k]];
+      }
+    }
+    __syncthreads();
+    bool more = false;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      if (a[k] != kNoAnc) {
+        ladd(&val[a[k]], v[k]);
+        const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
+        const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
+        a[k] = na;
+        link[tid + k * NT] = (uint32_t)na | (root << 16);
+        more |= na != kNoAnc;
+      }
+    }
+    if (!__syncthreads_or(more)) break;
+    if (round >= max_rounds) {
+      set_status(status, kStCycle);
+      break;
+    }
+  }
+  __syncthreads();
+
+  uint32_t nsx = 0;  // own nodes that leave the super-block
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = tid + k * NT;
+    const bool act = n < NN && (flag[n] & 1);
+    const int tl = n / CAP, j = n - tl * CAP;
+    const int ta = tl / G, tb = tl - ta * G;
+    const int64_t s = (dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j;
+    if (DOWN) {
+      if (act) ex_val[s] = (V)val[n];
+    } else {
+      const bool sbx_exit = act && (flag[n] & 2);
+      if (act) {
+        const int root = (int)(link[n] >> 16);
+        int64_t rs = -1;
+        if (flag[root] & 2) {
+          const int rtl = root / CAP, rj = root - rtl * CAP;
+          const int rta = rtl / G, rtb = rtl - rta * G;
+          rs = (dm.tile0 + (ty0 + rta) * dm.TX + tx0 + rtb) * CAP + rj;
+        }
+        sbroot[s] = (int32_t)rs;
+        if (sbx_exit) l2out[s] = (V)val[n];
+      }
+      if (sbx_exit) nsx |= 1u << k;
+    }
+  }
+  if (!DOWN) {
+    // Append the super-block exits to the global node list: one global
+    // atomic per workgroup, offsets from an LDS counter.
+    __shared__ uint32_t cnt, base;
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    const uint32_t mine = __builtin_popcount(nsx);
+    const uint32_t off = mine ? atomicAdd(&cnt, mine) : 0u;
+    __syncthreads();
+    if (tid == 0) base = cnt ? atomicAdd(&hdr[3], cnt) : 0u;
+    __syncthreads();
+    uint32_t w = base + off;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      if (nsx & (1u << k)) {
+        const int n = tid + k * NT;
+        const int tl = n / CAP, j = n - tl * CAP;
+        const int ta = tl / G, tb = tl - ta * G;
+        list[w++] = (int32_t)((dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j);
+      }
+    }
+  }
+}
+
+// Global resolve over super-block exits.  Node = a tile exit whose target
+// lies in another super-block; its parent is the super-block exit reached
+// from the target receiver (via the receiver's tile exit and that exit's
+// super-block root), or none.  Nodes are compacted into a list first.
+// Values V[s] plus a pending increment D[s]; round j folds D_j into V, then
+// sends the node's value to its 2^j-th ancestor's D_(j+1) with one atomic and
+// jumps the ancestor pointer.  The final value is V + D of the last round.
+template <typename V>
+__global__ void k_l2_init(const int32_t* __restrict__ list, const int32_t* __restrict__ sbroot, V* d0, V* d1,
+                          int32_t* a0, uint32_t* hdr) {
+  const int64_t n = hdr[3];
+  bool more = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = list[i];
+    const int32_t v = a0[s];  // the tile exit the target receiver leads to
+    const int32_t par = v >= 0 ? sbroot[v] : -1;
+    a0[s] = par;
+    d0[s] = 0;
+    d1[s] = 0;
+    more |= par >= 0;
+  }
+  if (more) hdr[64] = 1;
+}
+
+template <typename V>
+__global__ void k_l2_round(int j, const int32_t* __restrict__ list, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1,
+                           uint32_t* hdr) {
+  if (hdr[64 + j] == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && hdr[1] == 0xFFFFFFFFu) hdr[1] = (uint32_t)(j & 1);
+    return;
+  }
+  const int64_t n = hdr[3];
+  V* dc = (j & 1) ? d1 : d0;
+  V* dn = (j & 1) ? d0 : d1;
+  const int32_t* ac = (j & 1) ? a1 : a0;
+  int32_t* an = (j & 1) ? a0 : a1;
+  bool more = false;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = list[i];
+    const V v = val[s] + dc[s];
+    val[s] = v;
+    dc[s] = 0;
+    const int32_t a = ac[s];
+    int32_t a2 = -1;
+    if (a >= 0) {
+      vadd(&dn[a], v);
+      a2 = ac[a];
+    }
+    an[s] = a2;
+    more |= a2 >= 0;
+  }
+  if (more) hdr[64 + j + 1] = 1;
+}
+
+// Adds the last pending increment: the resolved value of every node.
+template <typename V>
+__global__ void k_l2_fold(const int32_t* __restrict__ list, V* val, const V* d0, const V* d1, const uint32_t* hdr) {
+  const int64_t n = hdr[3];
+  const V* d = (hdr[1] & 1) ? d1 : d0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = list[i];
+    val[s] += d[s];
+  }
+}
+
 // Backward: path sums H(e) = w(e) + H(parent(e)), w(e) = the receiver's
 // in-tile path sum, by pointer jumping (Wyllie).  Two buffers each.
 __global__ void k_bres_init(DemTable tab, int ts, int cap, int64_t nslots, const uint8_t* __restrict__ ex_code,
@@ -899,9 +1232,9 @@ __global__ void k_clear_flags(uint32_t* hdr) {
 
 // Builds the per-DEM table of a batch from the caller's device descriptors
 // (a serial prefix over the DEMs; n is small).
-__global__ void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int ts, DemInfo* out) {
+__global__ void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int ts, int bw, int bh, DemInfo* out) {
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int64_t t0 = 0;
+  int64_t t0 = 0, b0 = 0, s0 = 0;
   for (int32_t i = 0; i < n; ++i) {
     DemInfo d;
     d.off = desc[i].offset;
@@ -910,7 +1243,15 @@ __global__ void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int 
     d.TY = (d.H + ts - 1) / ts;
     d.TX = (d.W + ts - 1) / ts;
     d.tile0 = t0;
+    d.BY = (d.H + bh - 1) / bh;
+    d.BX = (d.W + bw - 1) / bw;
+    d.blk0 = b0;
+    d.SBY = (d.H + kSuper - 1) / kSuper;
+    d.SBX = (d.W + kSuper - 1) / kSuper;
+    d.sb0 = s0;
     t0 += (int64_t)d.TY * d.TX;
+    b0 += (int64_t)d.BY * d.BX;
+    s0 += (int64_t)d.SBY * d.SBX;
     out[i] = d;
   }
 }
@@ -929,9 +1270,10 @@ hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, DemInfo* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_demtab, dim3(1), dim3(64), 0, s, reinterpret_cast<const d8_desc*>(desc_dev), n, ts,
-                     out);
+hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, int bh, DemInfo* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_build_demtab, dim3(1), dim3(64), 0, s, reinterpret_cast<const d8_desc*>(desc_dev), n, ts, bw,
+                     bh, out);
   return hipGetLastError();
 }
 
@@ -940,46 +1282,54 @@ hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab,
   return hipGetLastError();
 }
 
-template <int TS, int NT>
-static hipError_t count_ts(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
+template <int BW, int BH, int TS>
+static hipError_t count_blk(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
+  constexpr int NT = BW * BH / kDblCpt;
   uint32_t* st = p.hdr;
-  const uint64_t* b0 = p.buf[0];
-  const uint64_t* b1 = p.buf[1];
-  const uint64_t* b2 = p.buf[2];
+  // the final pass reads the full exit areas the resolve left in ex_val
+  const uint64_t* b0 = p.ex_val;
+  const uint64_t* b1 = p.ex_val;
+  const uint64_t* b2 = p.ex_val;
   if (fin)
-    hipLaunchKernelGGL((k_tile_count<TS, NT, true>), dim3((unsigned)p.ntiles), dim3(NT), 0, s, dirs, p.tab, p.ntiles,
-                       p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
+    hipLaunchKernelGGL((k_block_count<BW, BH, TS, true>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, p.tab,
+                       p.nblocks, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
   else
-    hipLaunchKernelGGL((k_tile_count<TS, NT, false>), dim3((unsigned)p.ntiles), dim3(NT), 0, s, dirs, p.tab,
-                       p.ntiles, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
+    hipLaunchKernelGGL((k_block_count<BW, BH, TS, false>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, p.tab,
+                       p.nblocks, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
   return hipGetLastError();
+}
+
+// Block shape of the count passes for a tile side and wave count (whole
+// tiles per block, 16 cells per thread).
+void count_block_dims(int ts, int waves, int& bw, int& bh) {
+  if (ts == 32) {
+    bw = waves >= 2 ? 64 : 32;
+    bh = waves >= 4 ? 64 : 32;
+  } else {
+    bw = ts;
+    bh = ts;
+  }
 }
 
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
                               hipStream_t s) {
-  switch (p.ts) {
-    case 32:
-      if (nt <= 64) return count_ts<32, 64>(p, dirs, final_pass, out, s);
-      if (nt <= 128) return count_ts<32, 128>(p, dirs, final_pass, out, s);
-      return count_ts<32, 256>(p, dirs, final_pass, out, s);
-    case 64:
-      if (nt <= 128) return count_ts<64, 128>(p, dirs, final_pass, out, s);
-      if (nt <= 256) return count_ts<64, 256>(p, dirs, final_pass, out, s);
-      return count_ts<64, 512>(p, dirs, final_pass, out, s);
-    case 128:
-      if (nt <= 512) return count_ts<128, 512>(p, dirs, final_pass, out, s);
-      return count_ts<128, 1024>(p, dirs, final_pass, out, s);
-  }
+  (void)nt;
+  if (p.ts == 32 && p.bw == 32 && p.bh == 32) return count_blk<32, 32, 32>(p, dirs, final_pass, out, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 32) return count_blk<64, 32, 32>(p, dirs, final_pass, out, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 64) return count_blk<64, 64, 32>(p, dirs, final_pass, out, s);
+  if (p.ts == 64) return count_blk<64, 64, 64>(p, dirs, final_pass, out, s);
+  if (p.ts == 128) return count_blk<128, 128, 128>(p, dirs, final_pass, out, s);
   return hipErrorInvalidValue;
 }
 
 template <int TS>
 static hipError_t weighted_ts(const Plan& p, const uint8_t* dirs, const float* w, bool fin, float* out,
                               float* out_lo, int nt, hipStream_t s) {
-  const double* b0 = reinterpret_cast<const double*>(p.buf[0]);
-  const double* b1 = reinterpret_cast<const double*>(p.buf[1]);
-  const double* b2 = reinterpret_cast<const double*>(p.buf[2]);
   double* ev = reinterpret_cast<double*>(p.ex_val);
+  // the final pass reads the full exit areas the resolve left in ex_val
+  const double* b0 = ev;
+  const double* b1 = ev;
+  const double* b2 = ev;
   if (fin)
     hipLaunchKernelGGL((k_tile_weighted<TS, true>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, w, p.tab,
                        p.ntiles, p.cap, p.ex_code, p.rl, ev, b0, b1, b2, p.hdr, out, out_lo, p.hdr);
@@ -1022,25 +1372,44 @@ hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float
   return hipErrorInvalidValue;
 }
 
-template <typename V>
+template <int TS, typename LV, typename V, bool DOWN>
+static void group_launch(const Plan& p, hipStream_t s) {
+  V* ev = reinterpret_cast<V*>(p.ex_val);
+  V* b0 = reinterpret_cast<V*>(p.buf[0]);
+  V* b1 = reinterpret_cast<V*>(p.buf[1]);
+  V* b2 = reinterpret_cast<V*>(p.buf[2]);
+  hipLaunchKernelGGL((k_group<TS, LV, V, DOWN>), dim3((unsigned)p.nsb), dim3(512), 0, s, p.tab, p.nsb, p.ex_code,
+                     p.rl, ev, b0, p.anc[1], p.anc[0], p.list, b0, b1, b2, p.hdr, p.hdr);
+}
+
+template <typename LV, typename V, bool DOWN>
+static void group_pass(const Plan& p, hipStream_t s) {
+  switch (p.ts) {
+    case 32: group_launch<32, LV, V, DOWN>(p, s); break;
+    case 64: group_launch<64, LV, V, DOWN>(p, s); break;
+    default: group_launch<128, LV, V, DOWN>(p, s); break;
+  }
+}
+
+template <typename LV, typename V>
 static hipError_t fres(const Plan& p, hipStream_t s) {
   V* b0 = reinterpret_cast<V*>(p.buf[0]);
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   V* b2 = reinterpret_cast<V*>(p.buf[2]);
-  const V* ev = reinterpret_cast<const V*>(p.ex_val);
   const unsigned g = grid_for(p.nslots, 256);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
-  hipLaunchKernelGGL((k_fres_init<V>), dim3(g), dim3(256), 0, s, p.tab, p.ts, p.cap, p.nslots, p.ex_code, p.rl, ev,
-                     b0, b1, p.anc[0], p.hdr);
+  group_pass<LV, V, false>(p, s);
+  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.list, p.anc[1], b1, b2, p.anc[0], p.hdr);
   for (int j = 0; j < p.rounds; ++j)
-    hipLaunchKernelGGL((k_fres_round<V>), dim3(g), dim3(256), 0, s, j, p.nslots, p.ex_code, b0, b1, b2, p.anc[0],
-                       p.anc[1], p.hdr);
-  hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 3, p.hdr, p.hdr);
+    hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, p.list, b0, b1, b2, p.anc[0], p.anc[1], p.hdr);
+  hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
+  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, p.list, b0, b1, b2, p.hdr);
+  group_pass<LV, V, true>(p, s);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_resolve(const Plan& p, bool weighted, hipStream_t s) {
-  return weighted ? fres<double>(p, s) : fres<uint64_t>(p, s);
+  return weighted ? fres<double, double>(p, s) : fres<uint32_t, uint64_t>(p, s);
 }
 
 hipError_t launch_backward_resolve(const Plan& p, hipStream_t s) {
