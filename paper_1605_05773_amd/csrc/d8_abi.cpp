@@ -96,6 +96,8 @@ static DemInfo single_dem(int64_t rows, int64_t cols, int ts, int waves = 0) {
 
 static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves) {
   count_block_dims(p.ts, waves, p.bw, p.bh);
+  // counts: one wavefront per tile (a last-arriver walk) only when asked for
+  p.walk = (p.ts == 32 || p.ts == 64) && waves == 1;
   p.nblocks = 0;
   p.nsb = 0;
   if (hd) {

@@ -11,16 +11,20 @@ namespace d8 {
 
 // Workspace layout (all offsets 256-byte aligned):
 //   header   4096 B: [0] status word, [1] final-buffer index of the forward
-//            resolve, [2] of the backward resolve, [64..127] round flags
+//            resolve, [2] of the backward resolve, [3] super-block exit
+//            nodes, [64..127] round flags
 //   demtab   DemInfo x ndem                (batched calls only)
 //   ex_code  uint8  x nslots   direction code of an exit slot, 0xFF otherwise
 //   rl       uint16 x nslots   receiver slot -> exit slot of its in-tile path
 //   ex_val   8 B    x nslots   exit partial value (forward) / receiver path
 //                              sum (backward)
-//   buf[3]   8 B    x nslots   resolve values
-//   anc[2]   int32  x nslots   resolve ancestor pointers (anc[1] first holds
-//                              each tile exit's super-block root)
-//   list     int32  x nslots   compacted super-block exit slots
+//   buf[3]   8 B    x nslots   resolve values (forward: [0] values of the
+//                              super-block exits by dense node id, [1] and
+//                              [2] their pending increments)
+//   anc[2]   int32  x nslots   resolve ancestor pointers (forward: anc[0] the
+//                              nodes' ancestors by node id, anc[1] every tile
+//                              exit's super-block root node id)
+//   list     int32  x nslots   forward: second ancestor buffer of the nodes
 // A slot is one perimeter cell of one tile: slot id = tile * cap + perimeter
 // index (see perim_slot).
 struct Plan {
@@ -30,9 +34,10 @@ struct Plan {
   int64_t nslots = 0;
   int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
   int bw = 0, bh = 0;  // workgroup block of the count passes (whole tiles)
+  bool walk = false;   // count passes: one wavefront per tile (k_walk_count)
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
-  int32_t* list = nullptr;  // compacted super-block exit slots
+  int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes
   DemTable tab{};
   uint32_t* hdr = nullptr;
   DemInfo* demtab = nullptr;

@@ -14,6 +14,7 @@
 //   tile pass, final  each tile recomputes its internal area with the resolved
 //                     inflow of each receiver added, i.e. adds the incoming
 //                     areas along the receivers' downstream paths (Alg. 7-8).
+#include <algorithm>
 #include <type_traits>
 
 #include "d8_internal.hpp"
@@ -152,19 +153,21 @@ __device__ __forceinline__ int64_t slot_of_cell(const DemInfo& dm, int64_t gy, i
 // block, width and offset multiples of 4) the BH + 2 rows are fetched as
 // 32-bit words, all loads of a thread issued before any is consumed; the two
 // halo columns are single bytes.
-template <int BW, int BH>
+// NTC is the workgroup size when known at compile time (0: blockDim.x).
+template <int BW, int BH, int NTC = 0>
 __device__ __forceinline__ void load_halo(uint8_t* code, const uint8_t* __restrict__ dirs, const DemInfo& dm,
                                           int64_t y0, int64_t x0, int bw) {
   constexpr int HS = BW + 2;
   constexpr int HR = BH + 2;
   constexpr int WPR = BW / 4;     // 32-bit words per block row
   constexpr int NW = HR * WPR;    // rows y0-1 .. y0+BH
-  constexpr int MAXW = 9;
+  constexpr int MAXW = NTC ? (NW + NTC - 1) / NTC : 9;
+  constexpr int HL = NTC ? (2 * HR + NTC - 1) / NTC : 2;  // halo-column bytes per thread
   const uint8_t* D = dirs + dm.off;
   const int64_t H = dm.H, W = dm.W;
-  const int NT = blockDim.x, tid = threadIdx.x;
+  const int NT = NTC ? NTC : (int)blockDim.x, tid = threadIdx.x;
   const bool vec = bw == BW && (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(D + x0) & 3) == 0) &&
-                   (NW + NT - 1) / NT <= MAXW && HR <= NT;
+                   (NW + NT - 1) / NT <= MAXW && 2 * HR <= HL * NT;
   if (vec) {
     uint32_t v[MAXW];
 #pragma unroll
@@ -177,11 +180,13 @@ __device__ __forceinline__ void load_halo(uint8_t* code, const uint8_t* __restri
         if (gy >= 0 && gy < H) v[k] = *reinterpret_cast<const uint32_t*>(D + gy * W + x0 + 4 * q);
       }
     }
-    // halo columns x0-1 and x0+BW (2*HR bytes; at most two per thread)
-    uint8_t hb[2] = {kOutside, kOutside};
-    int hidx[2] = {-1, -1};
+    // halo columns x0-1 and x0+BW (2*HR bytes; at most HL per thread)
+    uint8_t hb[HL];
+    int hidx[HL];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < HL; ++k) {
+      hb[k] = kOutside;
+      hidx[k] = -1;
       const int i = tid + k * NT;
       if (i < 2 * HR) {
         const int lr = i >> 1, side = i & 1;
@@ -202,8 +207,9 @@ __device__ __forceinline__ void load_halo(uint8_t* code, const uint8_t* __restri
         o[3] = (uint8_t)(v[k] >> 24);
       }
     }
-    if (hidx[0] >= 0) code[hidx[0]] = hb[0];
-    if (hidx[1] >= 0) code[hidx[1]] = hb[1];
+#pragma unroll
+    for (int k = 0; k < HL; ++k)
+      if (hidx[k] >= 0) code[hidx[k]] = hb[k];
   } else {
     for (int i = tid; i < HS * HR; i += NT) {
       const int lr = i / HS, lc = i - lr * HS;
@@ -360,7 +366,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
   const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
   const int tid = threadIdx.x;
   D8_STAMP(0);
-  load_halo<BW, BH>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
+  load_halo<BW, BH, NT>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
   __syncthreads();
   D8_STAMP(1);
 
@@ -509,6 +515,265 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
             if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
                 sm.code[(R + 1 + ddr_t(k2)) * HS + C + 1 + ddc_t(k2)] != kNoData)
               link = (uint16_t)perim_slot(R - ta * TS, C - tb * TS, twc, thc);
+          }
+          rl[sb + j] = link;
+        }
+      }
+      ex_code[sb + j] = ec;
+    }
+  }
+  D8_STAMP(5);
+}
+
+// ------------------------------------------------------ counts: tile walk --
+// One wavefront owns one TS x TS tile (TS <= 64).  Tile-local area with the
+// inflows of other tiles left out (Alg. 2 with Alg. 3's unknowns), computed the
+// way Alg. 2 does it, by propagation in dependency order: every cell holds an
+// LDS word packing the sum of the areas that reached it so far with its count
+// of inputs still to arrive.  A lane starts at a source cell (no in-tile
+// input), adds its area to the target with one atomic that also retires one
+// pending input, and continues downstream only if it retired the last one
+// (Alg. 2's "last arriver continues"); otherwise it takes its next source.
+// Each lane's sources are its own cells, kept as a bit mask in registers, so a
+// refill costs no LDS traffic.  Every cell is stepped into exactly once.
+//
+// Walk code of an in-tile cell (a byte in LDS, replacing its direction):
+//   0..7          drains into the in-tile cell at that offset
+//   kWStop        outlet, or an invalid code / target (status raised)
+//   kWExit | d    drains in direction d into a valid cell of another tile
+//   kWInvalid     NoData, or beyond the DEM edge (ragged tile)
+constexpr uint32_t kWStop = 8;
+constexpr uint32_t kWInvalid = 9;
+constexpr uint32_t kWExit = 16;
+
+// Offsets of the eight directions in a row-major array of row stride HS, as
+// signed bytes packed into one word.
+__host__ __device__ constexpr uint64_t hoff_table(int hs) {
+  const int o[8] = {1, 1 - hs, -hs, -hs - 1, -1, hs - 1, hs, hs + 1};
+  uint64_t t = 0;
+  for (int i = 0; i < 8; ++i) t |= (uint64_t)(uint8_t)(int8_t)o[i] << (8 * i);
+  return t;
+}
+template <int HS>
+__device__ __forceinline__ int hoff(uint32_t d) {
+  static_assert(HS + 1 <= 127, "halo offsets must fit a signed byte");
+  constexpr uint64_t t = hoff_table(HS);
+  return (int)(int8_t)(uint8_t)(t >> (8 * d));
+}
+
+template <bool FINAL>
+struct WalkWord;
+template <>
+struct WalkWord<false> {  // tile-local areas only: at most 64 * 64
+  using T = uint32_t;
+  static constexpr int kShift = 28;
+};
+template <>
+struct WalkWord<true> {  // local area plus resolved inflows: up to 2^32 - 1
+  using T = uint64_t;
+  static constexpr int kShift = 40;
+};
+
+// Cell k of lane `lane` (k = 0 .. TS*TS/64 - 1): row and column in the tile.
+template <int TS>
+__device__ __forceinline__ void walk_cell(int lane, int k, int& r, int& c) {
+  constexpr int LPR = TS < 64 ? 64 / TS : 1;  // tile rows per wavefront row
+  r = k * LPR + (TS < 64 ? lane / TS : 0);
+  c = TS < 64 ? lane % TS : lane;
+}
+
+template <int TS, bool FINAL>
+__global__ __launch_bounds__(64) void k_walk_count(
+    const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles, int cap, uint8_t* __restrict__ ex_code,
+    uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val, const uint64_t* __restrict__ F,
+    uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+  static_assert(TS == 32 || TS == 64, "one wavefront per tile of side 32 or 64");
+  using A = typename WalkWord<FINAL>::T;
+  constexpr int PS = WalkWord<FINAL>::kShift;
+  constexpr A kOne = (A)1 << PS;  // one pending input
+  constexpr A kMask = kOne - 1;
+  constexpr int HS = TS + 2, NH = HS * HS, KPL = TS * TS / 64;
+  __shared__ A acc[NH];
+  __shared__ __attribute__((aligned(4))) uint8_t code[NH];
+  __shared__ int miss;
+  const int lane = threadIdx.x;
+  const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
+  D8_STAMP(0);
+  load_halo<TS, TS, 64>(code, dirs, g.dm, g.y0, g.x0, g.tw);
+  if (lane == 0) miss = 0;
+  __syncthreads();
+  D8_STAMP(1);
+
+  // Walk codes from the original directions (validated as in Alg. 1's setup).
+  uint32_t wpk[(KPL + 3) / 4];
+#pragma unroll
+  for (int q = 0; q < (KPL + 3) / 4; ++q) wpk[q] = 0;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    int r, c;
+    walk_cell<TS>(lane, k, r, c);
+    const int h = (r + 1) * HS + c + 1;
+    const uint32_t k0 = code[h];
+    uint32_t w;
+    if (r >= g.th || c >= g.tw || k0 == kNoData) {
+      w = kWInvalid;
+    } else if (k0 >= 8u) {
+      if (k0 != kNone) set_status(status, kStBadDir);
+      w = kWStop;
+    } else {
+      const int tr = r + ddr_t(k0), tc = c + ddc_t(k0);
+      const int64_t gy = g.y0 + tr, gx = g.x0 + tc;
+      if (gy < 0 || gy >= g.dm.H || gx < 0 || gx >= g.dm.W || code[h + hoff<HS>(k0)] == kNoData) {
+        set_status(status, kStBadDir);
+        w = kWStop;
+      } else {
+        w = (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) ? k0 : (kWExit | k0);
+      }
+    }
+    wpk[k >> 2] |= w << (8 * (k & 3));
+    acc[h] = 0;
+  }
+  // Receivers of the final pass: inflow = resolved areas of the exits of other
+  // tiles draining into them (Alg. 7's incoming area), read from the original
+  // codes of the halo.
+  A xin[FINAL ? (4 * TS - 4 + 63) / 64 : 1];
+  int xh[FINAL ? (4 * TS - 4 + 63) / 64 : 1];
+  if (FINAL) {
+    const int np = perim_count(g.tw, g.th);
+#pragma unroll
+    for (int q = 0; q < (4 * TS - 4 + 63) / 64; ++q) {
+      const int j = lane + 64 * q;
+      xin[q] = 0;
+      xh[q] = -1;
+      if (j < np) {
+        int lr, lc;
+        perim_cell(j, g.tw, g.th, lr, lc);
+        const int h = (lr + 1) * HS + lc + 1;
+        if (code[h] != kNoData) {
+          const uint32_t ext = input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th);
+          if (ext) {
+            xin[q] = (A)gather_inflow<uint64_t>(F, ext, lr, lc, g, TS, cap);
+            xh[q] = h;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  D8_STAMP(2);
+  // Replace directions by walk codes; count pending in-tile inputs.
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    int r, c;
+    walk_cell<TS>(lane, k, r, c);
+    const int h = (r + 1) * HS + c + 1;
+    const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+    code[h] = (uint8_t)w;
+    if (w < 8u) atomicAdd(&acc[h + hoff<HS>(w)], kOne);
+  }
+  if (FINAL) {
+#pragma unroll
+    for (int q = 0; q < (4 * TS - 4 + 63) / 64; ++q)
+      if (xh[q] >= 0) atomicAdd(&acc[xh[q]], xin[q]);
+  }
+  __syncthreads();
+  // Sources: valid cells with no pending input.
+  uint64_t src = 0;
+  int nvalid = 0;
+#pragma unroll
+  for (int k = 0; k < KPL; ++k) {
+    int r, c;
+    walk_cell<TS>(lane, k, r, c);
+    const int h = (r + 1) * HS + c + 1;
+    const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+    if (w != kWInvalid) {
+      ++nvalid;
+      if ((acc[h] >> PS) == 0) src |= 1ull << k;
+    }
+  }
+
+  D8_STAMP(3);
+  // The walk.
+  int h = -1;
+  uint32_t wc = 0;
+  A v = 0;
+  int nvis = 0;
+  for (;;) {
+    if (h < 0 && src != 0) {
+      const int k = __builtin_ctzll(src);
+      src &= src - 1;
+      int r, c;
+      walk_cell<TS>(lane, k, r, c);
+      h = (r + 1) * HS + c + 1;
+      wc = code[h];
+      v = FINAL ? (acc[h] & kMask) + 1 : (A)1;
+      ++nvis;
+    }
+    if (!__any(h >= 0)) break;
+    if (h >= 0) {
+      if (wc >= 8u) {
+        h = -1;
+      } else {
+        const int t = h + hoff<HS>(wc);
+        const A old = atomicAdd(&acc[t], v - kOne);
+        wc = code[t];
+        if ((old >> PS) == 1) {
+          h = t;
+          v = (old & kMask) + v + 1;
+          ++nvis;
+        } else {
+          h = -1;
+        }
+      }
+    }
+  }
+  D8_STAMP(4);
+  // A cell never reached sits on a cycle (its pending count never drops to 0):
+  // the wavefront's valid cells outnumber its steps.
+  if (nvis != nvalid) atomicAdd(&miss, nvalid - nvis);
+  __syncthreads();
+  if (lane == 0 && miss) set_status(status, kStCycle);
+
+  if (FINAL) {
+    uint32_t* O = out + g.dm.off;
+    const int64_t W = g.dm.W;
+#pragma unroll
+    for (int k = 0; k < KPL; ++k) {
+      int r, c;
+      walk_cell<TS>(lane, k, r, c);
+      const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
+      if (r < g.th && c < g.tw) {
+        const A a = acc[(r + 1) * HS + c + 1];
+        O[(g.y0 + r) * W + g.x0 + c] = w == kWInvalid ? 0u : (uint32_t)((a & kMask) + 1);
+      }
+    }
+  } else {
+    // Perimeter records (Alg. 4): exit partial areas, and for each receiver
+    // the exit its in-tile path leaves by (followed along the walk codes).
+    const int np = perim_count(g.tw, g.th);
+    const int64_t sb = g.tile * cap;
+    for (int j = lane; j < cap; j += 64) {
+      uint8_t ec = 0xFF;
+      if (j < np) {
+        int lr, lc;
+        perim_cell(j, g.tw, g.th, lr, lc);
+        const int h0 = (lr + 1) * HS + lc + 1;
+        const uint32_t w = code[h0];
+        if (w & kWExit) {
+          ec = (uint8_t)(w & 7u);
+          ex_val[sb + j] = (uint64_t)((acc[h0] & kMask) + 1);
+        }
+        if (w != kWInvalid && (input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th))) {
+          int t = h0;
+          uint32_t wt = w;
+          for (int n = 0; wt < 8u && n < TS * TS; ++n) {  // bounded: a cycle never ends
+            t += hoff<HS>(wt);
+            wt = code[t];
+          }
+          uint16_t link = 0xFFFF;
+          if (wt & kWExit) {
+            const int R = t / HS - 1, C = t - (t / HS) * HS - 1;
+            link = (uint16_t)perim_slot(R, C, g.tw, g.th);
           }
           rl[sb + j] = link;
         }
@@ -922,14 +1187,19 @@ struct GroupDims {
 __device__ __forceinline__ void ladd(uint32_t* p, uint32_t v) { atomicAdd(p, v); }
 __device__ __forceinline__ void ladd(double* p, double v) { atomicAdd(p, v); }
 
+// Up pass outputs: the super-block exits get dense node ids (in append
+// order; count in hdr[3]); l2val[id] = the exit's area within its super-block,
+// l2par[id] = the tile exit its target receiver leads to (-1: none), and for
+// every tile exit sbroot[slot] = the node id of the super-block exit its path
+// reaches (-1: it ends inside the super-block).  The down pass reads the
+// resolved node values from F (indexed through sbroot).
 template <int TS, typename LV, typename V, bool DOWN>
 __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const uint8_t* __restrict__ ex_code,
                                                const uint16_t* __restrict__ rl, V* __restrict__ ex_val,
-                                               V* __restrict__ l2out, int32_t* __restrict__ sbroot,
-                                               int32_t* __restrict__ tgt_exit, int32_t* __restrict__ list,
-                                               const V* __restrict__ F0, const V* __restrict__ F1,
-                                               const V* __restrict__ F2, uint32_t* __restrict__ hdr,
-                                               uint32_t* __restrict__ status) {
+                                               V* __restrict__ l2val, int32_t* __restrict__ sbroot,
+                                               int32_t* __restrict__ l2par, V* __restrict__ l2acc,
+                                               uint64_t* __restrict__ l2pend, const V* __restrict__ F,
+                                               uint32_t* __restrict__ hdr, uint32_t* __restrict__ status) {
   using D = GroupDims<TS, LV>;
   constexpr int G = D::G, CAP = D::CAP, NN = D::NN, NT = D::NT, NPT = D::NPT;
   __shared__ LV val[NN];
@@ -946,10 +1216,12 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   const int sbw = (int)min((int64_t)kSuper, (int64_t)dm.W - x0);
 
   uint16_t a[NPT];
+  int32_t tg[NPT];  // super-block exits: the tile exit the target receiver leads to
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tid + k * NT;
     a[k] = kNoAnc;
+    tg[k] = -1;
     if (n >= NN) continue;
     const int tl = n / CAP, j = n - tl * CAP;
     const int ta = tl / G, tb = tl - ta * G;
@@ -980,7 +1252,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
         // super-block exit: remember the tile exit its target receiver leads
         // to; the global resolve turns it into a parent via that exit's
         // super-block root
-        if (!DOWN) tgt_exit[s] = lk == 0xFFFF ? -1 : (int32_t)(tbase + lk);
+        tg[k] = lk == 0xFFFF ? -1 : (int32_t)(tbase + lk);
       }
     }
     val[n] = v;
@@ -991,7 +1263,6 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   if (DOWN) {
     // Resolved inflow of every receiver on the super-block's border, added at
     // the tile exit its in-tile path leaves by.
-    const V* F = F0;  // resolved super-block exit values
     const int P = perim_count(sbw, sbh);
     for (int i = tid; i < P; i += NT) {
       int r, c;
@@ -1005,7 +1276,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
         if (ny < 0 || ny >= dm.H || nx < 0 || nx >= dm.W) continue;
         const int64_t ns = slot_of_cell(dm, ny, nx, TS, CAP);
         const uint8_t ecn = ex_code[ns];
-        if (ecn < 8 && ny + ddr_t(ecn) == gy && nx + ddc_t(ecn) == gx) x += F[ns];
+        if (ecn < 8 && ny + ddr_t(ecn) == gy && nx + ddc_t(ecn) == gx) x += F[sbroot[ns]];
       }
       if (x != (V)0) {
         const int64_t tty = gy / TS, ttx = gx / TS;
@@ -1051,83 +1322,184 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   }
   __syncthreads();
 
+  if (DOWN) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int n = tid + k * NT;
+      if (n < NN && (flag[n] & 1)) {
+        const int tl = n / CAP, j = n - tl * CAP;
+        const int ta = tl / G, tb = tl - ta * G;
+        ex_val[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (V)val[n];
+      }
+    }
+    return;
+  }
+  // Dense node ids for the super-block exits: one global atomic per
+  // workgroup, offsets from an LDS counter.
   uint32_t nsx = 0;  // own nodes that leave the super-block
+  uint16_t root[NPT];
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tid + k * NT;
     const bool act = n < NN && (flag[n] & 1);
-    const int tl = n / CAP, j = n - tl * CAP;
-    const int ta = tl / G, tb = tl - ta * G;
-    const int64_t s = (dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j;
-    if (DOWN) {
-      if (act) ex_val[s] = (V)val[n];
-    } else {
-      const bool sbx_exit = act && (flag[n] & 2);
-      if (act) {
-        const int root = (int)(link[n] >> 16);
-        int64_t rs = -1;
-        if (flag[root] & 2) {
-          const int rtl = root / CAP, rj = root - rtl * CAP;
-          const int rta = rtl / G, rtb = rtl - rta * G;
-          rs = (dm.tile0 + (ty0 + rta) * dm.TX + tx0 + rtb) * CAP + rj;
-        }
-        sbroot[s] = (int32_t)rs;
-        if (sbx_exit) l2out[s] = (V)val[n];
-      }
-      if (sbx_exit) nsx |= 1u << k;
+    root[k] = act ? (uint16_t)(link[n] >> 16) : (uint16_t)0;
+    if (act && (flag[n] & 2)) nsx |= 1u << k;
+  }
+  __shared__ uint32_t cnt, base;
+  if (tid == 0) cnt = 0;
+  __syncthreads();
+  const uint32_t mine = __builtin_popcount(nsx);
+  const uint32_t off = mine ? atomicAdd(&cnt, mine) : 0u;
+  __syncthreads();
+  if (tid == 0) base = cnt ? atomicAdd(&hdr[3], cnt) : 0u;
+  __syncthreads();  // also: every root read before link is reused below
+  uint32_t w = base + off;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    if (nsx & (1u << k)) {
+      const int n = tid + k * NT;
+      link[n] = w;  // node id, looked up by the tile exits rooted here
+      l2val[w] = (V)val[n];
+      l2par[w] = tg[k];
+      l2acc[w] = 0;
+      l2pend[w] = 0;
+      ++w;
     }
   }
-  if (!DOWN) {
-    // Append the super-block exits to the global node list: one global
-    // atomic per workgroup, offsets from an LDS counter.
-    __shared__ uint32_t cnt, base;
-    if (tid == 0) cnt = 0;
-    __syncthreads();
-    const uint32_t mine = __builtin_popcount(nsx);
-    const uint32_t off = mine ? atomicAdd(&cnt, mine) : 0u;
-    __syncthreads();
-    if (tid == 0) base = cnt ? atomicAdd(&hdr[3], cnt) : 0u;
-    __syncthreads();
-    uint32_t w = base + off;
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) {
-      if (nsx & (1u << k)) {
-        const int n = tid + k * NT;
-        const int tl = n / CAP, j = n - tl * CAP;
-        const int ta = tl / G, tb = tl - ta * G;
-        list[w++] = (int32_t)((dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j);
+  for (int k = 0; k < NPT; ++k) {
+    const int n = tid + k * NT;
+    if (n < NN && (flag[n] & 1)) {
+      const int tl = n / CAP, j = n - tl * CAP;
+      const int ta = tl / G, tb = tl - ta * G;
+      const int r = root[k];
+      sbroot[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (flag[r] & 2) ? (int32_t)link[r] : -1;
+    }
+  }
+}
+
+// Global resolve over super-block exits.  Node = a super-block exit (dense
+// id); its parent is the super-block exit reached from its target receiver
+// (via the receiver's tile exit and that exit's super-block root), or none.
+// The nodes form a forest and each needs the sum of its subtree (Alg. 6's
+// accumulation over the master's graph).  Two stages:
+//  1. propagation in dependency order as in Alg. 2, one thread per leaf: a
+//     finished node adds its value to its parent and retires one of the
+//     parent's pending children with the same atomic; the thread that retires
+//     the last one finishes the parent and carries on.  Each edge costs one
+//     atomic and no two threads contend for more than a node's children.  A
+//     thread stops after kL2Steps nodes (long chains would serialise), parking
+//     the node it finished last;
+//  2. doubling over what is left (unfinished nodes with the partial sums they
+//     have received, and parked nodes with their full values): value V[i]
+//     plus a pending increment D[i]; round j folds D_j into V, sends the
+//     node's value to its 2^j-th ancestor's D_(j+1) and jumps the ancestor
+//     pointer; O(log depth) launches.  Nodes finished in stage 1 take no part.
+// Counts keep the stage-1 state in one 64-bit word per node (bits 0..39 the
+// sum received, bits 40..62 the children still to arrive); weighted values
+// keep an fp64 sum and a pending count whose bit 31 marks a node with
+// children, a child's addition being fenced before its retirement.
+constexpr int kL2Shift = 40;
+constexpr uint64_t kL2One = 1ull << kL2Shift;
+constexpr uint64_t kL2Mask = kL2One - 1;
+constexpr uint32_t kL2HasKids = 0x80000000u;
+constexpr int kL2Steps = 64;
+
+// Parent ids: -1 root; <= -2 a parked node (parent -(p + 2)).
+template <typename V>
+__global__ void k_l2_init(const int32_t* __restrict__ sbroot, int32_t* par, V* acc, uint64_t* pend, uint32_t* hdr) {
+  const int64_t n = hdr[3];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = par[i];  // the tile exit the target receiver leads to
+    const int32_t pa = v >= 0 ? sbroot[v] : -1;
+    par[i] = pa;
+    if (pa >= 0) {
+      if constexpr (std::is_same<V, uint64_t>::value) {
+        atomicAdd(&acc[pa], kL2One);
+      } else {
+        uint32_t* pc = reinterpret_cast<uint32_t*>(&pend[pa]);
+        atomicOr(pc, kL2HasKids);
+        atomicAdd(pc, 1u);
       }
     }
   }
 }
 
-// Global resolve over super-block exits.  Node = a tile exit whose target
-// lies in another super-block; its parent is the super-block exit reached
-// from the target receiver (via the receiver's tile exit and that exit's
-// super-block root), or none.  Nodes are compacted into a list first.
-// Values V[s] plus a pending increment D[s]; round j folds D_j into V, then
-// sends the node's value to its 2^j-th ancestor's D_(j+1) with one atomic and
-// jumps the ancestor pointer.  The final value is V + D of the last round.
 template <typename V>
-__global__ void k_l2_init(const int32_t* __restrict__ list, const int32_t* __restrict__ sbroot, V* d0, V* d1,
-                          int32_t* a0, uint32_t* hdr) {
+__global__ void k_l2_walk(int32_t* par, V* val, V* acc, uint64_t* pend, const uint32_t* __restrict__ hdr) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)hdr[3]) return;
+  bool leaf;
+  if constexpr (std::is_same<V, uint64_t>::value)
+    leaf = acc[i] == 0;  // never received anything: no children
+  else
+    leaf = *reinterpret_cast<const uint32_t*>(&pend[i]) == 0;
+  if (!leaf) return;
+  int32_t s = (int32_t)i;
+  V v = val[s];
+  for (int step = 0;; ++step) {
+    const int32_t pa = par[s];
+    if (pa < 0) break;
+    if (step == kL2Steps) {
+      par[s] = -(pa + 2);  // parked: finished, not yet added to its parent
+      break;
+    }
+    if constexpr (std::is_same<V, uint64_t>::value) {
+      const uint64_t old = atomicAdd(&acc[pa], v - kL2One);
+      if ((old >> kL2Shift) != 1) break;
+      v = val[pa] + (old & kL2Mask) + v;
+    } else {
+      unsafeAtomicAdd(&acc[pa], v);
+      __threadfence();
+      const uint32_t old = atomicSub(reinterpret_cast<uint32_t*>(&pend[pa]), 1u);
+      if ((old & ~kL2HasKids) != 1u) break;
+      __threadfence();
+      v = val[pa] + __hip_atomic_load(&acc[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    val[pa] = v;
+    s = pa;
+  }
+}
+
+// Stage-2 start: ancestor = parent for unfinished and parked nodes (-1 for
+// nodes finished and delivered), unfinished nodes fold in what they received,
+// pending increments zeroed (they reuse the stage-1 words).
+template <typename V>
+__global__ void k_l2_prep(int32_t* anc, V* val, V* d0, V* d1, const uint64_t* pend, uint32_t* hdr) {
   const int64_t n = hdr[3];
   bool more = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s = list[i];
-    const int32_t v = a0[s];  // the tile exit the target receiver leads to
-    const int32_t par = v >= 0 ? sbroot[v] : -1;
-    a0[s] = par;
-    d0[s] = 0;
-    d1[s] = 0;
-    more |= par >= 0;
+    const int32_t pa = anc[i];
+    int32_t a = -1;
+    if (pa <= -2) {
+      a = -pa - 2;
+    } else {
+      bool unfinished;
+      V part;
+      if constexpr (std::is_same<V, uint64_t>::value) {
+        const uint64_t w = d0[i];
+        unfinished = (w >> kL2Shift) != 0;
+        part = w & kL2Mask;
+      } else {
+        unfinished = (*reinterpret_cast<const uint32_t*>(&pend[i]) & ~kL2HasKids) != 0;
+        part = d0[i];
+      }
+      if (unfinished) {
+        val[i] += part;
+        a = pa;
+      }
+    }
+    anc[i] = a;
+    d0[i] = 0;
+    d1[i] = 0;
+    more |= a >= 0;
   }
   if (more) hdr[64] = 1;
 }
 
 template <typename V>
-__global__ void k_l2_round(int j, const int32_t* __restrict__ list, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1,
-                           uint32_t* hdr) {
+__global__ void k_l2_round(int j, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1, uint32_t* hdr) {
   if (hdr[64 + j] == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && hdr[1] == 0xFFFFFFFFu) hdr[1] = (uint32_t)(j & 1);
     return;
@@ -1139,17 +1511,21 @@ __global__ void k_l2_round(int j, const int32_t* __restrict__ list, V* val, V* d
   int32_t* an = (j & 1) ? a0 : a1;
   bool more = false;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s = list[i];
-    const V v = val[s] + dc[s];
-    val[s] = v;
-    dc[s] = 0;
-    const int32_t a = ac[s];
+    const int32_t a = ac[i];
+    const V d = dc[i];
+    if (a < 0 && d == (V)0) {  // nothing to fold or send
+      an[i] = -1;
+      continue;
+    }
+    const V v = val[i] + d;
+    val[i] = v;
+    dc[i] = 0;
     int32_t a2 = -1;
     if (a >= 0) {
       vadd(&dn[a], v);
       a2 = ac[a];
     }
-    an[s] = a2;
+    an[i] = a2;
     more |= a2 >= 0;
   }
   if (more) hdr[64 + j + 1] = 1;
@@ -1157,13 +1533,11 @@ __global__ void k_l2_round(int j, const int32_t* __restrict__ list, V* val, V* d
 
 // Adds the last pending increment: the resolved value of every node.
 template <typename V>
-__global__ void k_l2_fold(const int32_t* __restrict__ list, V* val, const V* d0, const V* d1, const uint32_t* hdr) {
+__global__ void k_l2_fold(V* val, const V* d0, const V* d1, const uint32_t* hdr) {
   const int64_t n = hdr[3];
   const V* d = (hdr[1] & 1) ? d1 : d0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t s = list[i];
-    val[s] += d[s];
-  }
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    val[i] += d[i];
 }
 
 // Backward: path sums H(e) = w(e) + H(parent(e)), w(e) = the receiver's
@@ -1311,9 +1685,23 @@ void count_block_dims(int ts, int waves, int& bw, int& bh) {
   }
 }
 
+template <int TS>
+static hipError_t count_walk(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
+  // the final pass reads the full exit areas the resolve left in ex_val
+  if (fin)
+    hipLaunchKernelGGL((k_walk_count<TS, true>), dim3((unsigned)p.ntiles), dim3(64), 0, s, dirs, p.tab, p.ntiles,
+                       p.cap, p.ex_code, p.rl, p.ex_val, p.ex_val, out, p.hdr);
+  else
+    hipLaunchKernelGGL((k_walk_count<TS, false>), dim3((unsigned)p.ntiles), dim3(64), 0, s, dirs, p.tab, p.ntiles,
+                       p.cap, p.ex_code, p.rl, p.ex_val, p.ex_val, out, p.hdr);
+  return hipGetLastError();
+}
+
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
                               hipStream_t s) {
   (void)nt;
+  if (p.walk && p.ts == 32) return count_walk<32>(p, dirs, final_pass, out, s);
+  if (p.walk && p.ts == 64) return count_walk<64>(p, dirs, final_pass, out, s);
   if (p.ts == 32 && p.bw == 32 && p.bh == 32) return count_blk<32, 32, 32>(p, dirs, final_pass, out, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 32) return count_blk<64, 32, 32>(p, dirs, final_pass, out, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 64) return count_blk<64, 64, 32>(p, dirs, final_pass, out, s);
@@ -1377,9 +1765,9 @@ static void group_launch(const Plan& p, hipStream_t s) {
   V* ev = reinterpret_cast<V*>(p.ex_val);
   V* b0 = reinterpret_cast<V*>(p.buf[0]);
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
-  V* b2 = reinterpret_cast<V*>(p.buf[2]);
+  uint64_t* b2 = p.buf[2];
   hipLaunchKernelGGL((k_group<TS, LV, V, DOWN>), dim3((unsigned)p.nsb), dim3(512), 0, s, p.tab, p.nsb, p.ex_code,
-                     p.rl, ev, b0, p.anc[1], p.anc[0], p.list, b0, b1, b2, p.hdr, p.hdr);
+                     p.rl, ev, b0, p.anc[1], p.anc[0], b1, b2, b0, p.hdr, p.hdr);
 }
 
 template <typename LV, typename V, bool DOWN>
@@ -1396,14 +1784,19 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
   V* b0 = reinterpret_cast<V*>(p.buf[0]);
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   V* b2 = reinterpret_cast<V*>(p.buf[2]);
-  const unsigned g = grid_for(p.nslots, 256);
+  // nodes: at most one per super-block perimeter cell
+  const unsigned g = grid_for(std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper), 256);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
   group_pass<LV, V, false>(p, s);
-  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.list, p.anc[1], b1, b2, p.anc[0], p.hdr);
+  uint64_t* pend = p.buf[2];
+  const unsigned gn = (unsigned)std::max<int64_t>(1, (std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper) + 255) / 256);
+  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
   for (int j = 0; j < p.rounds; ++j)
-    hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, p.list, b0, b1, b2, p.anc[0], p.anc[1], p.hdr);
+    hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, p.hdr);
   hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
-  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, p.list, b0, b1, b2, p.hdr);
+  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, p.hdr);
   group_pass<LV, V, true>(p, s);
   return hipGetLastError();
 }
