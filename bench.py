@@ -29,10 +29,11 @@ sys.path.insert(0, ROOT)
 METRIC = "Gcells/s D8 accumulation + % HBM roofline; fwd+bwd vs plain fwd Gcells/s"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per cell of each kernel phase (minimal model):
-#   count_tile_final : 1 B direction in + 4 B count out
-#   count_tile_emit  : 1 B direction in
+#   count_tile_emit  : 1 B direction in + 4 B tile-local count out
+#   count_tile_final : 1 B direction in (the read-modify-write of the cells
+#                      downstream of receivers depends on the data)
 #   flowdirs         : 4 B elevation in + 1 B direction out
-ALG_BYTES_PER_CELL = {"count_tile_final": 5.0, "count_tile_emit": 1.0, "flowdirs": 5.0,
+ALG_BYTES_PER_CELL = {"count_tile_emit": 5.0, "count_tile_final": 1.0, "flowdirs": 5.0,
                       "weighted_tile_final": 9.0, "weighted_tile_emit": 5.0,
                       "backward_tile_final": 9.0, "backward_tile_emit": 5.0}
 OP_BYTES_PER_CELL = 5.0  # d8_accum counts: 1 B direction in + 4 B count out

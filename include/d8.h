@@ -86,6 +86,16 @@ typedef struct {
  * only).  No workspace. */
 d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream);
 
+/* Steepest-slope variant (Sec. 3 states the D8 rule as the largest drop over
+ * the distance to the neighbour, distance 1 for E, N, W, S and sqrt(2) for the
+ * diagonals; Sec. 1 as the lowest neighbour, which d8_flowdirs follows).  Same
+ * arguments, NoData and edge rules as d8_flowdirs.  The slope to neighbour d
+ * is evaluated in double precision as (z_cell - z_d) * f_d, f_d = 1 or
+ * 1/sqrt(2) rounded to double; the largest strictly positive slope wins, ties
+ * to the first in E,NE,N,NW,W,SW,S,SE order; with no positive slope the cell
+ * gets 8.  Exact for that definition.  No workspace. */
+d8_status d8_flowdirs_steepest(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* Up-slope area (Eq. 1) over a direction field. */
 

@@ -47,11 +47,12 @@ def lib():
             raise RuntimeError("oracle/_oracle.so is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(_SO)
         P, I = ctypes.c_void_p, ctypes.c_int64
-        for name in ("orc_flowdirs", "orc_accum_u32", "orc_accum_f64", "orc_backward_f64",
+        for name in ("orc_flowdirs", "orc_flowdirs_steepest", "orc_accum_u32", "orc_accum_f64", "orc_backward_f64",
                      "orc_bruteforce_f64", "orc_backward_f64d", "orc_accum_f64d"):
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
         L.orc_flowdirs.argtypes = [P, I, I, P]
+        L.orc_flowdirs_steepest.argtypes = [P, I, I, P]
         L.orc_accum_u32.argtypes = [P, I, I, P]
         L.orc_accum_f64.argtypes = [P, I, I, P, P]
         L.orc_accum_f64d.argtypes = [P, I, I, P, P]
@@ -78,10 +79,13 @@ def _check(st):
         raise OracleError(st)
 
 
-def flowdirs(z: np.ndarray) -> np.ndarray:
+def flowdirs(z: np.ndarray, rule: str = "lowest") -> np.ndarray:
+    """D8 codes: rule "lowest" (lowest of eight) or "steepest" (largest drop
+    over distance, diagonals at sqrt 2)."""
     z = _c(z, np.float32)
     out = np.empty(z.shape, dtype=np.uint8)
-    _check(lib().orc_flowdirs(z.ctypes.data, z.shape[0], z.shape[1], out.ctypes.data))
+    fn = {"lowest": lib().orc_flowdirs, "steepest": lib().orc_flowdirs_steepest}[rule]
+    _check(fn(z.ctypes.data, z.shape[0], z.shape[1], out.ctypes.data))
     return out
 
 

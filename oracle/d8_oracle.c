@@ -35,6 +35,7 @@
  * fixture, the recursion identity, the outlet-sum invariant, linearity and the
  * adjoint dot-product identity).
  */
+#define _GNU_SOURCE /* M_SQRT1_2 */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -66,6 +67,37 @@ int orc_flowdirs(const float* z, int64_t H, int64_t W, uint8_t* dirs) {
       for (int d = 0; d < 8; ++d) {
         float n = z[(r + ODR[d]) * W + c + ODC[d]];
         if (n < best) { best = n; k = d; }
+      }
+      dirs[i] = (uint8_t)k;
+    }
+  }
+  return ORC_OK;
+}
+
+/* D8 steepest-slope direction field: the slope rule with diagonal distance of
+ * Sec. 3 (drop divided by the distance to the neighbour: 1 for E, N, W, S and
+ * sqrt(2) for the diagonals).  The slope of neighbour d is evaluated in double
+ * as (z_c - z_d) * f_d with f_d = 1 or 1/sqrt(2) (rounded to double); the
+ * largest strictly positive slope wins, ties to the first in E..SE order; no
+ * positive slope -> outlet (8).  Edge and NoData rules as orc_flowdirs. */
+int orc_flowdirs_steepest(const float* z, int64_t H, int64_t W, uint8_t* dirs) {
+  for (int64_t r = 0; r < H; ++r) {
+    for (int64_t c = 0; c < W; ++c) {
+      int64_t i = r * W + c;
+      float v = z[i];
+      if (isnan(v)) { dirs[i] = 255; continue; }
+      if (r == 0 || c == 0 || r == H - 1 || c == W - 1) { dirs[i] = 8; continue; }
+      int nan_adj = 0;
+      for (int d = 0; d < 8; ++d)
+        if (isnan(z[(r + ODR[d]) * W + c + ODC[d]])) nan_adj = 1;
+      if (nan_adj) { dirs[i] = 8; continue; }
+      double best = 0.0;
+      int k = 8;
+      for (int d = 0; d < 8; ++d) {
+        double n = (double)z[(r + ODR[d]) * W + c + ODC[d]];
+        double f = (ODR[d] != 0 && ODC[d] != 0) ? M_SQRT1_2 : 1.0;
+        double s = ((double)v - n) * f;
+        if (s > best) { best = s; k = d; }
       }
       dirs[i] = (uint8_t)k;
     }

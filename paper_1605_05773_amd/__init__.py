@@ -15,6 +15,7 @@ if libd8.so is missing every call raises.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import torch
@@ -50,6 +51,7 @@ def lib():
         P, I64, I32, SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
         sig = {
             "d8_flowdirs": ([P, I64, I64, P, P], I32),
+            "d8_flowdirs_steepest": ([P, I64, I64, P, P], I32),
             "d8_workspace_bytes": ([I64, I64, I32], SZ),
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
@@ -73,7 +75,7 @@ def lib():
 
 
 EXPORTED = (
-    "d8_flowdirs", "d8_workspace_bytes", "d8_accum", "d8_accum_backward", "d8_batched_workspace_bytes",
+    "d8_flowdirs", "d8_flowdirs_steepest", "d8_workspace_bytes", "d8_accum", "d8_accum_backward", "d8_batched_workspace_bytes",
     "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
 )
@@ -115,14 +117,17 @@ def workspace(nbytes: int, device) -> torch.Tensor:
     return cur[pad:pad + nbytes]
 
 
-def flowdirs(dem: torch.Tensor) -> torch.Tensor:
-    """D8 'lowest of eight' codes of a float32 DEM (NaN = NoData)."""
+def flowdirs(dem: torch.Tensor, rule: str = "lowest") -> torch.Tensor:
+    """D8 codes of a float32 DEM (NaN = NoData): rule "lowest" (lowest of
+    eight) or "steepest" (largest drop over distance, diagonals at sqrt 2)."""
     dem = _dev_tensor(dem, torch.float32, "dem")
     if dem.dim() != 2:
         raise ValueError("dem must be 2-D")
+    fn = {"lowest": "d8_flowdirs", "steepest": "d8_flowdirs_steepest"}.get(rule)
+    if fn is None:
+        raise ValueError(f"unknown rule {rule!r}")
     out = torch.empty(dem.shape, dtype=torch.uint8, device=dem.device)
-    _check(lib().d8_flowdirs(dem.data_ptr(), dem.shape[0], dem.shape[1], out.data_ptr(), _stream(dem.device)),
-           "d8_flowdirs")
+    _check(getattr(lib(), fn)(dem.data_ptr(), dem.shape[0], dem.shape[1], out.data_ptr(), _stream(dem.device)), fn)
     return out
 
 
@@ -312,3 +317,104 @@ def accum_backward_batched(batch: Batch, dirs_packed, g_packed, *, tile=0, waves
                                            ws.data_ptr(), ws.numel(), tile, waves, _stream(batch.device)),
            "d8_accum_backward_batched")
     return out
+
+
+# ---------------------------------------------------------------- autotune --
+
+def _bucket(batch: Batch) -> str:
+    """Size bucket of a batch: DEM count, total cells and longest side, each
+    rounded to a power of two."""
+    def p2(x):
+        return 1 << max(0, int(x - 1).bit_length())
+    side = max(max(r, c) for r, c in batch.shapes)
+    return f"n{p2(batch.n)}_cells{p2(batch.total)}_side{p2(side)}"
+
+
+def autotune_batched(batch: Batch, dirs_packed, w_packed, *, cache_path=None):
+    """Fastest (tile, waves) of the batched forward+backward on these inputs.
+
+    Runs d8_autotune_batched (it synchronises the stream) unless cache_path
+    (a JSON file) already holds a result for the batch's size bucket; new
+    results are written back.  Returns (tile, waves, ms)."""
+    key = _bucket(batch)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
+        if key in cache:
+            e = cache[key]
+            return int(e["tile"]), int(e["waves"]), float(e["ms"])
+    dirs_packed = _dev_tensor(dirs_packed, torch.uint8, "dirs_packed")
+    w_packed = _dev_tensor(w_packed, torch.float32, "w_packed")
+    out = torch.empty(batch.total, dtype=torch.float32, device=batch.device)
+    g = torch.empty(batch.total, dtype=torch.float32, device=batch.device)
+    ws = workspace(batch.workspace_bytes(32), batch.device)
+    bt, bw, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0)
+    _check(lib().d8_autotune_batched(dirs_packed.data_ptr(), ctypes.addressof(batch.host_desc),
+                                     batch.dev_desc.data_ptr(), batch.n, w_packed.data_ptr(), out.data_ptr(),
+                                     g.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.byref(bt), ctypes.byref(bw),
+                                     ctypes.byref(ms), _stream(batch.device)), "d8_autotune_batched")
+    res = (bt.value, bw.value, ms.value)
+    if cache_path:
+        cache[key] = {"tile": res[0], "waves": res[1], "ms": res[2]}
+        tmp = f"{cache_path}.tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache_path)
+    return res
+
+
+# ----------------------------------------------------------- graph launch --
+
+class BatchedGraph:
+    """The batched weighted forward and its backward captured once as a HIP
+    graph (torch.cuda.CUDAGraph is a HIP graph under ROCm) over fixed device
+    buffers; replay() re-runs both on whatever the input buffers hold.
+
+    Every library call only enqueues kernels on the current stream (no
+    allocation, synchronisation or memset), so the sequence is capturable.
+    Inputs: the `dirs`, `w` and `g` tensors (packed, fixed addresses) —
+    overwrite them in place between replays.  Outputs: `area` and `grad`."""
+
+    def __init__(self, batch: Batch, *, tile=0, waves=0):
+        self.batch = batch
+        dev = batch.device
+        n = batch.total
+        self.dirs = torch.zeros(n, dtype=torch.uint8, device=dev)
+        self.w = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.g = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.area = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.grad = torch.zeros(n, dtype=torch.float32, device=dev)
+        nb = batch.workspace_bytes(tile)
+        raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        pad = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[pad:pad + nb]
+        self.tile, self.waves = tile, waves
+        self.graph = None
+
+    def _enqueue(self):
+        accum_batched(self.batch, self.dirs, self.w, tile=self.tile, waves=self.waves, out=self.area, ws=self.ws)
+        accum_backward_batched(self.batch, self.dirs, self.g, tile=self.tile, waves=self.waves, out=self.grad,
+                               ws=self.ws)
+
+    def capture(self):
+        s = torch.cuda.Stream(device=self.batch.device)
+        s.wait_stream(torch.cuda.current_stream(self.batch.device))
+        with torch.cuda.stream(s):
+            self._enqueue()  # warm-up outside the graph
+        torch.cuda.current_stream(self.batch.device).wait_stream(s)
+        torch.cuda.synchronize(self.batch.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+        return self
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+        return self.area, self.grad
+
+    def status(self) -> int:
+        return device_status(self.ws)

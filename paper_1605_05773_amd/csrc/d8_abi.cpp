@@ -96,8 +96,6 @@ static DemInfo single_dem(int64_t rows, int64_t cols, int ts, int waves = 0) {
 
 static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves) {
   count_block_dims(p.ts, waves, p.bw, p.bh);
-  // counts: one wavefront per tile (a last-arriver walk) only when asked for
-  p.walk = (p.ts == 32 || p.ts == 64) && waves == 1;
   p.nblocks = 0;
   p.nsb = 0;
   if (hd) {
@@ -199,14 +197,23 @@ const char* d8_strerror(d8_status s) {
   return "unknown status";
 }
 
-d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream) {
+static d8_status flowdirs_rule(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream,
+                               bool steepest) {
   if (!dem || !dirs || !shape_ok(rows, cols)) return D8_EINVAL;
   DemTable tab{};
   tab.n = 1;
   tab.one = single_dem(rows, cols, kFlowdirsBlock);
   const int64_t nb = (int64_t)tab.one.TY * tab.one.TX;
   PhaseScope ps(kPhFlowdirs, (hipStream_t)stream);
-  return hip_status(launch_flowdirs(dem, dirs, tab, nb, (hipStream_t)stream));
+  return hip_status(launch_flowdirs(dem, dirs, tab, nb, (hipStream_t)stream, steepest));
+}
+
+d8_status d8_flowdirs(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream) {
+  return flowdirs_rule(dem, rows, cols, dirs, stream, false);
+}
+
+d8_status d8_flowdirs_steepest(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, void* stream) {
+  return flowdirs_rule(dem, rows, cols, dirs, stream, true);
 }
 
 size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile) {
@@ -239,7 +246,7 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
     const int nt = pick_threads(p.ts, waves, false);
     {
       PhaseScope ps(kPhCountEmit, s);
-      if ((e = launch_count_tiles(p, dirs, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+      if ((e = launch_count_tiles(p, dirs, false, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
     }
     {
       PhaseScope ps(kPhCountResolve, s);
@@ -254,7 +261,8 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
     const int nt = pick_threads(p.ts, waves, false);
     {
       PhaseScope ps(kPhWEmit, s);
-      if ((e = launch_weighted_tiles(p, dirs, w, false, nullptr, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+      if ((e = launch_weighted_tiles(p, dirs, w, false, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
+        return D8_EHIP;
     }
     {
       PhaseScope ps(kPhWResolve, s);

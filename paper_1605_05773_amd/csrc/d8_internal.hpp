@@ -34,7 +34,6 @@ struct Plan {
   int64_t nslots = 0;
   int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
   int bw = 0, bh = 0;  // workgroup block of the count passes (whole tiles)
-  bool walk = false;   // count passes: one wavefront per tile (k_walk_count)
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes
@@ -57,7 +56,8 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base);
 // Launchers (return hipError_t of the last launch).
 // Flow directions over 64x64-cell blocks (tab built with tile side 64).
 constexpr int kFlowdirsBlock = 64;
-hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s);
+hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s,
+                           bool steepest = false);
 hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, int bh, DemInfo* out,
                                hipStream_t s);
 void count_block_dims(int ts, int waves, int& bw, int& bh);

@@ -22,9 +22,10 @@
 
 namespace d8 {
 
-// Optional per-phase cycle stamps for measurement builds (no-op here).
+// Optional per-phase cycle stamps for measurement builds (no-op here):
+// D8_STAMP(pass, i) marks the start of phase i of pass 0 (emit) or 1.
 #ifndef D8_STAMP
-#define D8_STAMP(i)
+#define D8_STAMP(pass, i)
 #endif
 
 constexpr uint64_t kValMask = (1ull << 40) - 1;
@@ -51,6 +52,29 @@ __device__ __forceinline__ uint8_t lowest8(float c, float n0, float n1, float n2
   return k;
 }
 
+// Steepest-slope variant (the drop-over-distance rule of Sec. 3): slope to a
+// neighbour = drop / distance, distance sqrt(2) for the diagonals, evaluated
+// in double as (c - n) * f with f = 1 or 1/sqrt(2) rounded to double; the
+// largest strictly positive slope wins, ties to the first in E..SE order.
+__device__ __forceinline__ uint8_t steepest8(float c, float n0, float n1, float n2, float n3, float n4, float n5,
+                                             float n6, float n7) {
+  constexpr double kDiag = 0.70710678118654752440;
+  const double z = (double)c;
+  double best = 0.0;
+  uint8_t k = kNone;
+  double s;
+  s = (z - (double)n0);         if (s > best) { best = s; k = 0; }
+  s = (z - (double)n1) * kDiag; if (s > best) { best = s; k = 1; }
+  s = (z - (double)n2);         if (s > best) { best = s; k = 2; }
+  s = (z - (double)n3) * kDiag; if (s > best) { best = s; k = 3; }
+  s = (z - (double)n4);         if (s > best) { best = s; k = 4; }
+  s = (z - (double)n5) * kDiag; if (s > best) { best = s; k = 5; }
+  s = (z - (double)n6);         if (s > best) { best = s; k = 6; }
+  s = (z - (double)n7) * kDiag; if (s > best) { best = s; k = 7; }
+  return k;
+}
+
+template <bool STEEP>
 __global__ __launch_bounds__(256) void k_flowdirs(const float* __restrict__ dem, uint8_t* __restrict__ dirs,
                                                    DemTable tab) {
   const int64_t tile = blockIdx.x;
@@ -94,7 +118,9 @@ __global__ __launch_bounds__(256) void k_flowdirs(const float* __restrict__ dem,
         const bool nanadj = __builtin_isnan(n0) | __builtin_isnan(n1) | __builtin_isnan(n2) |
                             __builtin_isnan(n3) | __builtin_isnan(n4) | __builtin_isnan(n5) |
                             __builtin_isnan(n6) | __builtin_isnan(n7);
-        k = nanadj ? kNone : lowest8(c, n0, n1, n2, n3, n4, n5, n6, n7);
+        k = nanadj ? kNone
+                   : (STEEP ? steepest8(c, n0, n1, n2, n3, n4, n5, n6, n7)
+                            : lowest8(c, n0, n1, n2, n3, n4, n5, n6, n7));
       }
       code[b] = k;
     }
@@ -322,9 +348,9 @@ constexpr int kDblCpt = 16;  // cells per thread
 // ancestor or kNoAnc; high 16 bits: the ancestor at distance
 // min(2^j, distance to the tile root), i.e. the root once the exact
 // ancestor has run out).
-template <int BW, int BH>
+template <int BW, int BH, typename V>
 struct DblSmem {
-  uint32_t val[BW * BH];
+  V val[BW * BH];
   uint32_t link[BW * BH];
   uint8_t code[(BW + 2) * (BH + 2)];
 };
@@ -351,26 +377,45 @@ __device__ __forceinline__ BlockGeo block_geo(const DemTable& tab, int64_t blk) 
   return b;
 }
 
-template <int BW, int BH, int TS, bool FINAL>
-__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
-    const uint8_t* __restrict__ dirs, DemTable tab, int64_t nblocks, int cap, uint8_t* __restrict__ ex_code,
-    uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val, const uint64_t* __restrict__ F0,
-    const uint64_t* __restrict__ F1, const uint64_t* __restrict__ F2, const uint32_t* __restrict__ hdr,
-    uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
+// Values: V = uint32_t for counts (w = 1; integer sums, so the result does
+// not depend on the order of the atomic additions), V = double for weights
+// (fp64 sums: the rounding of any order is far below float32 output
+// precision).  The pass writes the tile-local areas to the output and the
+// perimeter records of every tile; the finalising pass adds the inflows.
+template <int BW, int BH, int TS, typename V>
+__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
+    const uint8_t* __restrict__ dirs, const float* __restrict__ w, DemTable tab, int64_t nblocks, int cap,
+    uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, void* __restrict__ ex_val, void* __restrict__ out,
+    float* __restrict__ out_lo, uint32_t* __restrict__ status) {
+  constexpr bool kCount = std::is_same<V, uint32_t>::value;
+  using EV = std::conditional_t<kCount, uint64_t, double>;  // exit values for the resolve
   constexpr int NC = BW * BH;
   constexpr int NT = NC / kDblCpt;
   constexpr int HS = BW + 2;
   constexpr int TPX = BW / TS, TPY = BH / TS;  // tiles per block row / column
   static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
-  __shared__ DblSmem<BW, BH> sm;
+  __shared__ DblSmem<BW, BH, V> sm;
   const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
   const int tid = threadIdx.x;
-  D8_STAMP(0);
+  const int64_t W = g.dm.W;
+  const int64_t base = g.dm.off + g.y0 * W + g.x0;  // the block's first cell
+  D8_STAMP(0, 0);
+  float wv[kCount ? 1 : kDblCpt];
+  if (!kCount) {
+#pragma unroll
+    for (int k = 0; k < kDblCpt; ++k) {
+      const int c = tid + k * NT;
+      const int r = c / BW, col = c % BW;
+      wv[k] = (w && r < g.bh && col < g.bw) ? w[base + r * W + col] : 1.0f;
+    }
+  }
   load_halo<BW, BH, NT>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
   __syncthreads();
-  D8_STAMP(1);
+  D8_STAMP(0, 1);
 
-  // Setup: in-tile target (ancestor at distance 1) and initial value.
+  // Setup: in-tile target (ancestor at distance 1) and initial value.  Only
+  // blocks on the DEM's border can have targets off the grid.
+  const bool border = g.y0 == 0 || g.x0 == 0 || g.y0 + BH >= g.dm.H || g.x0 + BW >= g.dm.W;
   uint16_t a[kDblCpt];
 #pragma unroll
   for (int k = 0; k < kDblCpt; ++k) {
@@ -386,57 +431,27 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
     const bool drains = ok && code < 8u;
     const bool inside = drains && tr >= 0 && tr < th && tc >= 0 && tc < tw;
     const uint8_t tcode = sm.code[(r + 1 + dr) * HS + col + 1 + dc];
-    if (ok && (code > 8u || (drains && tcode == kNoData) ||
-               (drains && !inside &&
-                (g.y0 + r + dr < 0 || g.y0 + r + dr >= g.dm.H || g.x0 + col + dc < 0 || g.x0 + col + dc >= g.dm.W)))) {
-      set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
-    }
+    bool bad = ok && (code > 8u || (drains && tcode == kNoData));
+    if (border)
+      bad |= drains && !inside &&
+             (g.y0 + r + dr < 0 || g.y0 + r + dr >= g.dm.H || g.x0 + col + dc < 0 || g.x0 + col + dc >= g.dm.W);
+    if (bad) set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
     a[k] = (inside && tcode != kNoData) ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
-    sm.val[c] = ok ? 1u : 0u;
+    if constexpr (kCount)
+      sm.val[c] = ok ? 1u : 0u;
+    else
+      sm.val[c] = ok ? (double)wv[k] : 0.0;
     sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
   }
   __syncthreads();
-  if (FINAL) {
-    // Inflow of every receiver: the resolved areas of the exits of other
-    // tiles that drain into it (the paper's incoming area, Alg. 7).
-    const uint64_t* F;
-    {
-      const uint32_t fi = hdr[1];
-      F = fi == 0 ? F0 : (fi == 1 ? F1 : F2);
-    }
-    for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
-      const int tl = idx / cap, j = idx - tl * cap;
-      const int ta = tl / TPX, tb = tl - ta * TPX;
-      const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
-      if (th <= 0 || tw <= 0) continue;
-      const int thc = min(TS, th), twc = min(TS, tw);
-      if (j >= perim_count(twc, thc)) continue;
-      int lr, lc;
-      perim_cell(j, twc, thc, lr, lc);
-      const int r = ta * TS + lr, col = tb * TS + lc;
-      if (sm.code[(r + 1) * HS + col + 1] == kNoData) continue;
-      const uint32_t ext = input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc);
-      if (ext) {
-        TileGeo tg;
-        tg.dm = g.dm;
-        tg.y0 = g.y0 + ta * TS;
-        tg.x0 = g.x0 + tb * TS;
-        tg.th = thc;
-        tg.tw = twc;
-        sm.val[r * BW + col] += (uint32_t)gather_inflow<uint64_t>(F, ext, lr, lc, tg, TS, cap);
-      }
-    }
-    __syncthreads();
-  }
-  D8_STAMP(2);
-  D8_STAMP(3);
+  D8_STAMP(0, 2);
 
   // Doubling rounds.  Reads of a round (own value, ancestor's link word) all
   // happen before the barrier, updates after it.  The saturating pointer
   // becomes the ancestor's saturating pointer when the exact one runs out.
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
   for (int round = 0;; ++round) {
-    uint32_t v[kDblCpt];
+    V v[kDblCpt];
     uint32_t nl[kDblCpt];
 #pragma unroll
     for (int k = 0; k < kDblCpt; ++k) {
@@ -465,86 +480,72 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_count(
     }
   }
   __syncthreads();
-  D8_STAMP(4);
+  D8_STAMP(0, 3);
 
-  if (FINAL) {
-    uint32_t* O = out + g.dm.off;
-    const int64_t W = g.dm.W;
+  // Tile-local areas.
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
-      const int c = tid + k * NT;
-      const int r = c / BW, col = c % BW;
-      if (r < g.bh && col < g.bw) O[(g.y0 + r) * W + g.x0 + col] = sm.val[c];
-    }
-  } else {
-    // Perimeter records of every tile of the block: exit values, and for each
-    // receiver the exit its in-tile path leaves by.
-    for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
-      const int tl = idx / cap, j = idx - tl * cap;
-      const int ta = tl / TPX, tb = tl - ta * TPX;
-      const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
-      if (th <= 0 || tw <= 0) continue;  // tile beyond the DEM edge
-      const int thc = min(TS, th), twc = min(TS, tw);
-      const int64_t sb = (g.dm.tile0 + (g.ty0 + ta) * g.dm.TX + g.tx0 + tb) * cap;
-      uint8_t ec = 0xFF;
-      if (j < perim_count(twc, thc)) {
-        int lr, lc;
-        perim_cell(j, twc, thc, lr, lc);
-        const int r = ta * TS + lr, col = tb * TS + lc;
-        const uint32_t code = sm.code[(r + 1) * HS + col + 1];
-        if (code < 8u) {
-          const int tr = lr + ddr_t(code), tc = lc + ddc_t(code);
-          if (!(tr >= 0 && tr < thc && tc >= 0 && tc < twc)) {
-            const int64_t gy = g.y0 + r + ddr_t(code), gx = g.x0 + col + ddc_t(code);
-            if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
-                sm.code[(r + 1 + ddr_t(code)) * HS + col + 1 + ddc_t(code)] != kNoData) {
-              ec = (uint8_t)code;
-              ex_val[sb + j] = (uint64_t)sm.val[r * BW + col];
-            }
-          }
-        }
-        if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
-          // Receiver: the root of its in-tile path is the exit it leaves by,
-          // unless the path ends at an outlet.
-          const int root = (int)(sm.link[r * BW + col] >> 16);
-          const int R = root / BW, C = root % BW;
-          const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
-          uint16_t link = 0xFFFF;
-          if (k2 < 8u) {
-            const int64_t gy = g.y0 + R + ddr_t(k2), gx = g.x0 + C + ddc_t(k2);
-            if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
-                sm.code[(R + 1 + ddr_t(k2)) * HS + C + 1 + ddc_t(k2)] != kNoData)
-              link = (uint16_t)perim_slot(R - ta * TS, C - tb * TS, twc, thc);
-          }
-          rl[sb + j] = link;
-        }
+  for (int k = 0; k < kDblCpt; ++k) {
+    const int c = tid + k * NT;
+    const int r = c / BW, col = c % BW;
+    if (r < g.bh && col < g.bw) {
+      const int64_t o = base + r * W + col;
+      if constexpr (kCount) {
+        static_cast<uint32_t*>(out)[o] = sm.val[c];
+      } else {
+        const double x = sm.val[c];
+        const float hi = (float)x;
+        static_cast<float*>(out)[o] = hi;
+        if (out_lo) out_lo[o] = (float)(x - (double)hi);
       }
-      ex_code[sb + j] = ec;
     }
   }
-  D8_STAMP(5);
+  D8_STAMP(0, 4);
+  // Perimeter records of every tile of the block (Alg. 4): exit values, and
+  // for each receiver the exit its in-tile path leaves by.
+  for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
+    const int tl = idx / cap, j = idx - tl * cap;
+    const int ta = tl / TPX, tb = tl - ta * TPX;
+    const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
+    if (th <= 0 || tw <= 0) continue;  // tile beyond the DEM edge
+    const int thc = min(TS, th), twc = min(TS, tw);
+    const int64_t sb = (g.dm.tile0 + (g.ty0 + ta) * g.dm.TX + g.tx0 + tb) * cap;
+    uint8_t ec = 0xFF;
+    if (j < perim_count(twc, thc)) {
+      int lr, lc;
+      perim_cell(j, twc, thc, lr, lc);
+      const int r = ta * TS + lr, col = tb * TS + lc;
+      const uint32_t code = sm.code[(r + 1) * HS + col + 1];
+      if (code < 8u) {
+        const int tr = lr + ddr_t(code), tc = lc + ddc_t(code);
+        if (!(tr >= 0 && tr < thc && tc >= 0 && tc < twc)) {
+          const int64_t gy = g.y0 + r + ddr_t(code), gx = g.x0 + col + ddc_t(code);
+          if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
+              sm.code[(r + 1 + ddr_t(code)) * HS + col + 1 + ddc_t(code)] != kNoData) {
+            ec = (uint8_t)code;
+            static_cast<EV*>(ex_val)[sb + j] = (EV)sm.val[r * BW + col];
+          }
+        }
+      }
+      if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
+        // Receiver: the root of its in-tile path is the exit it leaves by,
+        // unless the path ends at an outlet.
+        const int root = (int)(sm.link[r * BW + col] >> 16);
+        const int R = root / BW, C = root % BW;
+        const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
+        uint16_t link = 0xFFFF;
+        if (k2 < 8u) {
+          const int64_t gy = g.y0 + R + ddr_t(k2), gx = g.x0 + C + ddc_t(k2);
+          if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
+              sm.code[(R + 1 + ddr_t(k2)) * HS + C + 1 + ddc_t(k2)] != kNoData)
+            link = (uint16_t)perim_slot(R - ta * TS, C - tb * TS, twc, thc);
+        }
+        rl[sb + j] = link;
+      }
+    }
+    ex_code[sb + j] = ec;
+  }
+  D8_STAMP(0, 5);
 }
-
-// ------------------------------------------------------ counts: tile walk --
-// One wavefront owns one TS x TS tile (TS <= 64).  Tile-local area with the
-// inflows of other tiles left out (Alg. 2 with Alg. 3's unknowns), computed the
-// way Alg. 2 does it, by propagation in dependency order: every cell holds an
-// LDS word packing the sum of the areas that reached it so far with its count
-// of inputs still to arrive.  A lane starts at a source cell (no in-tile
-// input), adds its area to the target with one atomic that also retires one
-// pending input, and continues downstream only if it retired the last one
-// (Alg. 2's "last arriver continues"); otherwise it takes its next source.
-// Each lane's sources are its own cells, kept as a bit mask in registers, so a
-// refill costs no LDS traffic.  Every cell is stepped into exactly once.
-//
-// Walk code of an in-tile cell (a byte in LDS, replacing its direction):
-//   0..7          drains into the in-tile cell at that offset
-//   kWStop        outlet, or an invalid code / target (status raised)
-//   kWExit | d    drains in direction d into a valid cell of another tile
-//   kWInvalid     NoData, or beyond the DEM edge (ragged tile)
-constexpr uint32_t kWStop = 8;
-constexpr uint32_t kWInvalid = 9;
-constexpr uint32_t kWExit = 16;
 
 // Offsets of the eight directions in a row-major array of row stride HS, as
 // signed bytes packed into one word.
@@ -556,393 +557,150 @@ __host__ __device__ constexpr uint64_t hoff_table(int hs) {
 }
 template <int HS>
 __device__ __forceinline__ int hoff(uint32_t d) {
-  static_assert(HS + 1 <= 127, "halo offsets must fit a signed byte");
-  constexpr uint64_t t = hoff_table(HS);
-  return (int)(int8_t)(uint8_t)(t >> (8 * d));
+  if constexpr (HS + 1 <= 127) {
+    constexpr uint64_t t = hoff_table(HS);
+    return (int)(int8_t)(uint8_t)(t >> (8 * d));
+  } else {
+    return ddr_t(d) * HS + ddc_t(d);
+  }
 }
 
-template <bool FINAL>
-struct WalkWord;
-template <>
-struct WalkWord<false> {  // tile-local areas only: at most 64 * 64
-  using T = uint32_t;
-  static constexpr int kShift = 28;
-};
-template <>
-struct WalkWord<true> {  // local area plus resolved inflows: up to 2^32 - 1
-  using T = uint64_t;
-  static constexpr int kShift = 40;
-};
-
-// Cell k of lane `lane` (k = 0 .. TS*TS/64 - 1): row and column in the tile.
-template <int TS>
-__device__ __forceinline__ void walk_cell(int lane, int k, int& r, int& c) {
-  constexpr int LPR = TS < 64 ? 64 / TS : 1;  // tile rows per wavefront row
-  r = k * LPR + (TS < 64 ? lane / TS : 0);
-  c = TS < 64 ? lane % TS : lane;
-}
-
-template <int TS, bool FINAL>
-__global__ __launch_bounds__(64) void k_walk_count(
-    const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles, int cap, uint8_t* __restrict__ ex_code,
-    uint16_t* __restrict__ rl, uint64_t* __restrict__ ex_val, const uint64_t* __restrict__ F,
-    uint32_t* __restrict__ out, uint32_t* __restrict__ status) {
-  static_assert(TS == 32 || TS == 64, "one wavefront per tile of side 32 or 64");
-  using A = typename WalkWord<FINAL>::T;
-  constexpr int PS = WalkWord<FINAL>::kShift;
-  constexpr A kOne = (A)1 << PS;  // one pending input
-  constexpr A kMask = kOne - 1;
-  constexpr int HS = TS + 2, NH = HS * HS, KPL = TS * TS / 64;
-  __shared__ A acc[NH];
+// ------------------------------------------------------- finalising pass --
+// Alg. 7-8: each receiver's incoming area (the resolved areas of the exits of
+// other tiles that drain into it) is added to every cell on its downstream
+// path inside the tile.  The emit pass already wrote the tile-local areas, so
+// only the cells downstream of receivers change: each receiver with inflow
+// walks its path accumulating into an LDS array (paths may share cells; the
+// sums are exact for counts and fp64 for weights), then the touched cells of
+// the output are updated.
+template <int TS, typename V>
+__global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
+                                               int cap, const void* __restrict__ F, void* __restrict__ out,
+                                               float* __restrict__ out_lo) {
+  constexpr bool kCount = std::is_same<V, uint32_t>::value;
+  using FV = std::conditional_t<kCount, uint64_t, double>;  // resolved exit values
+  constexpr int HS = TS + 2, NH = HS * HS, NC = TS * TS, NT = 256;
+  constexpr int NRX = (4 * TS - 4 + NT - 1) / NT;  // perimeter cells per thread
   __shared__ __attribute__((aligned(4))) uint8_t code[NH];
-  __shared__ int miss;
-  const int lane = threadIdx.x;
+  __shared__ V Y[NH];  // indexed like code (row stride HS)
+  __shared__ int any;
+  const int tid = threadIdx.x;
   const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
-  D8_STAMP(0);
-  load_halo<TS, TS, 64>(code, dirs, g.dm, g.y0, g.x0, g.tw);
-  if (lane == 0) miss = 0;
+  D8_STAMP(1, 0);
+  load_halo<TS, TS, NT>(code, dirs, g.dm, g.y0, g.x0, g.tw);
+  for (int i = tid; i < NH; i += NT) Y[i] = 0;
+  if (tid == 0) any = 0;
   __syncthreads();
-  D8_STAMP(1);
-
-  // Walk codes from the original directions (validated as in Alg. 1's setup).
-  uint32_t wpk[(KPL + 3) / 4];
+  // Inflow of every receiver (from the original halo codes).
+  const FV* Fv = static_cast<const FV*>(F);
+  const int np = perim_count(g.tw, g.th);
+  V xr[NRX];
+  int hr[NRX];
 #pragma unroll
-  for (int q = 0; q < (KPL + 3) / 4; ++q) wpk[q] = 0;
-#pragma unroll
-  for (int k = 0; k < KPL; ++k) {
-    int r, c;
-    walk_cell<TS>(lane, k, r, c);
-    const int h = (r + 1) * HS + c + 1;
-    const uint32_t k0 = code[h];
-    uint32_t w;
-    if (r >= g.th || c >= g.tw || k0 == kNoData) {
-      w = kWInvalid;
-    } else if (k0 >= 8u) {
-      if (k0 != kNone) set_status(status, kStBadDir);
-      w = kWStop;
-    } else {
-      const int tr = r + ddr_t(k0), tc = c + ddc_t(k0);
-      const int64_t gy = g.y0 + tr, gx = g.x0 + tc;
-      if (gy < 0 || gy >= g.dm.H || gx < 0 || gx >= g.dm.W || code[h + hoff<HS>(k0)] == kNoData) {
-        set_status(status, kStBadDir);
-        w = kWStop;
-      } else {
-        w = (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) ? k0 : (kWExit | k0);
-      }
-    }
-    wpk[k >> 2] |= w << (8 * (k & 3));
-    acc[h] = 0;
-  }
-  // Receivers of the final pass: inflow = resolved areas of the exits of other
-  // tiles draining into them (Alg. 7's incoming area), read from the original
-  // codes of the halo.
-  A xin[FINAL ? (4 * TS - 4 + 63) / 64 : 1];
-  int xh[FINAL ? (4 * TS - 4 + 63) / 64 : 1];
-  if (FINAL) {
-    const int np = perim_count(g.tw, g.th);
-#pragma unroll
-    for (int q = 0; q < (4 * TS - 4 + 63) / 64; ++q) {
-      const int j = lane + 64 * q;
-      xin[q] = 0;
-      xh[q] = -1;
-      if (j < np) {
-        int lr, lc;
-        perim_cell(j, g.tw, g.th, lr, lc);
-        const int h = (lr + 1) * HS + lc + 1;
-        if (code[h] != kNoData) {
-          const uint32_t ext = input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th);
-          if (ext) {
-            xin[q] = (A)gather_inflow<uint64_t>(F, ext, lr, lc, g, TS, cap);
-            xh[q] = h;
-          }
+  for (int q = 0; q < NRX; ++q) {
+    const int j = tid + q * NT;
+    xr[q] = 0;
+    hr[q] = -1;
+    if (j < np) {
+      int lr, lc;
+      perim_cell(j, g.tw, g.th, lr, lc);
+      const int h = (lr + 1) * HS + lc + 1;
+      if (code[h] != kNoData) {
+        const uint32_t ext = input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th);
+        if (ext) {
+          xr[q] = (V)gather_inflow<FV>(Fv, ext, lr, lc, g, TS, cap);
+          hr[q] = h;
         }
       }
     }
   }
   __syncthreads();
-  D8_STAMP(2);
-  // Replace directions by walk codes; count pending in-tile inputs.
-#pragma unroll
-  for (int k = 0; k < KPL; ++k) {
-    int r, c;
-    walk_cell<TS>(lane, k, r, c);
-    const int h = (r + 1) * HS + c + 1;
-    const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-    code[h] = (uint8_t)w;
-    if (w < 8u) atomicAdd(&acc[h + hoff<HS>(w)], kOne);
-  }
-  if (FINAL) {
-#pragma unroll
-    for (int q = 0; q < (4 * TS - 4 + 63) / 64; ++q)
-      if (xh[q] >= 0) atomicAdd(&acc[xh[q]], xin[q]);
+  // Fence the tile: the halo ring becomes kOutside, so a walk stops where its
+  // path leaves the tile (cells beyond the DEM already hold kOutside).
+  for (int i = tid; i < 4 * HS - 4; i += NT) {
+    int h;
+    if (i < HS) h = i;                                  // top row
+    else if (i < 2 * HS) h = (HS - 1) * HS + (i - HS);  // bottom row
+    else if (i < 3 * HS - 2) h = (i - 2 * HS + 1) * HS; // left column
+    else h = (i - 3 * HS + 4) * HS - 1;                 // right column
+    code[h] = kOutside;
   }
   __syncthreads();
-  // Sources: valid cells with no pending input.
-  uint64_t src = 0;
-  int nvalid = 0;
+  D8_STAMP(1, 1);
+  // Walks: add the inflow at every cell of the receiver's in-tile path.
 #pragma unroll
-  for (int k = 0; k < KPL; ++k) {
-    int r, c;
-    walk_cell<TS>(lane, k, r, c);
-    const int h = (r + 1) * HS + c + 1;
-    const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-    if (w != kWInvalid) {
-      ++nvalid;
-      if ((acc[h] >> PS) == 0) src |= 1ull << k;
+  for (int q = 0; q < NRX; ++q) {
+    if (hr[q] < 0 || xr[q] == (V)0) continue;
+    any = 1;
+    const V x = xr[q];
+    int h = hr[q];
+    for (int n = 0; n < NC; ++n) {  // bounded: a cycle never ends
+      const uint32_t k = code[h];
+      if (k >= kOutside) break;  // left the tile, or a NoData target (flagged by the emit pass)
+      atomicAdd(&Y[h], x);
+      if (k >= 8u) break;        // outlet (or an invalid code, flagged by the emit pass)
+      h += hoff<HS>(k);
     }
   }
-
-  D8_STAMP(3);
-  // The walk.
-  int h = -1;
-  uint32_t wc = 0;
-  A v = 0;
-  int nvis = 0;
-  for (;;) {
-    if (h < 0 && src != 0) {
-      const int k = __builtin_ctzll(src);
-      src &= src - 1;
-      int r, c;
-      walk_cell<TS>(lane, k, r, c);
-      h = (r + 1) * HS + c + 1;
-      wc = code[h];
-      v = FINAL ? (acc[h] & kMask) + 1 : (A)1;
-      ++nvis;
-    }
-    if (!__any(h >= 0)) break;
-    if (h >= 0) {
-      if (wc >= 8u) {
-        h = -1;
-      } else {
-        const int t = h + hoff<HS>(wc);
-        const A old = atomicAdd(&acc[t], v - kOne);
-        wc = code[t];
-        if ((old >> PS) == 1) {
-          h = t;
-          v = (old & kMask) + v + 1;
-          ++nvis;
-        } else {
-          h = -1;
-        }
-      }
-    }
-  }
-  D8_STAMP(4);
-  // A cell never reached sits on a cycle (its pending count never drops to 0):
-  // the wavefront's valid cells outnumber its steps.
-  if (nvis != nvalid) atomicAdd(&miss, nvalid - nvis);
   __syncthreads();
-  if (lane == 0 && miss) set_status(status, kStCycle);
-
-  if (FINAL) {
-    uint32_t* O = out + g.dm.off;
-    const int64_t W = g.dm.W;
-#pragma unroll
-    for (int k = 0; k < KPL; ++k) {
-      int r, c;
-      walk_cell<TS>(lane, k, r, c);
-      const uint32_t w = (wpk[k >> 2] >> (8 * (k & 3))) & 0xFFu;
-      if (r < g.th && c < g.tw) {
-        const A a = acc[(r + 1) * HS + c + 1];
-        O[(g.y0 + r) * W + g.x0 + c] = w == kWInvalid ? 0u : (uint32_t)((a & kMask) + 1);
-      }
-    }
-  } else {
-    // Perimeter records (Alg. 4): exit partial areas, and for each receiver
-    // the exit its in-tile path leaves by (followed along the walk codes).
-    const int np = perim_count(g.tw, g.th);
-    const int64_t sb = g.tile * cap;
-    for (int j = lane; j < cap; j += 64) {
-      uint8_t ec = 0xFF;
-      if (j < np) {
-        int lr, lc;
-        perim_cell(j, g.tw, g.th, lr, lc);
-        const int h0 = (lr + 1) * HS + lc + 1;
-        const uint32_t w = code[h0];
-        if (w & kWExit) {
-          ec = (uint8_t)(w & 7u);
-          ex_val[sb + j] = (uint64_t)((acc[h0] & kMask) + 1);
-        }
-        if (w != kWInvalid && (input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th))) {
-          int t = h0;
-          uint32_t wt = w;
-          for (int n = 0; wt < 8u && n < TS * TS; ++n) {  // bounded: a cycle never ends
-            t += hoff<HS>(wt);
-            wt = code[t];
-          }
-          uint16_t link = 0xFFFF;
-          if (wt & kWExit) {
-            const int R = t / HS - 1, C = t - (t / HS) * HS - 1;
-            link = (uint16_t)perim_slot(R, C, g.tw, g.th);
-          }
-          rl[sb + j] = link;
-        }
-      }
-      ex_code[sb + j] = ec;
-    }
+  D8_STAMP(1, 2);
+  if (!any) {
+    D8_STAMP(1, 3);
+    D8_STAMP(1, 4);
+    D8_STAMP(1, 5);
+    return;
   }
-  D8_STAMP(5);
-}
-
-// ------------------------------------------ weighted: gather-style tile walk --
-// Values are float32 pairs (hi, lo).  The arrival that retires a cell's last
-// pending input sums the cell as w (+ resolved inflow) + the inputs' values in
-// the fixed order E..SE, so the result does not depend on arrival order.
-template <int TS>
-struct WSmem {
-  df val[TS * TS];
-  uint32_t pend[TS * TS / 4];  // one byte per cell
-  uint8_t cv[TS * TS];         // validated code
-  uint8_t inm[TS * TS];        // in-tile input mask
-  uint8_t code[(TS + 2) * (TS + 2)];
-};
-
-__device__ __forceinline__ int noff(int i, int ts) { return ddr(i) * ts + ddc(i); }
-
-template <int TS, bool FINAL>
-__global__ __launch_bounds__(1024) void k_tile_weighted(const uint8_t* __restrict__ dirs,
-                                                        const float* __restrict__ wts, DemTable tab, int64_t ntiles,
-                                                        int cap, uint8_t* __restrict__ ex_code,
-                                                        uint16_t* __restrict__ rl, double* __restrict__ ex_val,
-                                                        const double* __restrict__ F0, const double* __restrict__ F1,
-                                                        const double* __restrict__ F2,
-                                                        const uint32_t* __restrict__ hdr, float* __restrict__ out,
-                                                        float* __restrict__ out_lo, uint32_t* __restrict__ status) {
-  __shared__ WSmem<TS> sm;
-  constexpr int HS = TS + 2;
-  const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
-  const int NT = blockDim.x, tid = threadIdx.x;
-  const int cpt = (TS * TS + NT - 1) / NT;
-  load_codes<TS>(sm.code, dirs, g);
-  __syncthreads();
-  const double* F = nullptr;
-  if (FINAL) {
-    const uint32_t fi = hdr[1];
-    F = fi == 0 ? F0 : (fi == 1 ? F1 : F2);
-  }
-  const float* Wp = wts ? wts + g.dm.off : nullptr;
+  // All loads of a thread are issued before any store (the stores could
+  // otherwise alias the next loads and serialise them).
+  constexpr int KPT = NC / NT;
+  static_assert(KPT * NT == NC, "whole tile per pass");
+  const int64_t base = g.dm.off + g.y0 * g.dm.W + g.x0;
   const int64_t W = g.dm.W;
-  uint8_t* pendb = reinterpret_cast<uint8_t*>(sm.pend);
-  uint64_t src = 0;
-  for (int k = 0; k < cpt; ++k) {
-    const int c = tid + k * NT;
-    if (c >= TS * TS) break;
-    const int r = c / TS, col = c % TS;
-    df v = {0.0f, 0.0f};
-    uint8_t e = kNoData, m = 0, p = 0;
-    if (r < g.th && col < g.tw && sm.code[(r + 1) * HS + col + 1] != kNoData) {
-      e = eff_code<TS>(sm.code, r, col, g, status);
-      int pend;
-      uint32_t inm, ext;
-      inputs_of<TS>(sm.code, r, col, g, pend, inm, ext);
-      v.hi = Wp ? Wp[(g.y0 + r) * W + g.x0 + col] : 1.0f;
-      if (FINAL && ext) v = df_add(v, df_from_double(gather_inflow<double>(F, ext, r, col, g, TS, cap)));
-      m = (uint8_t)inm;
-      p = (uint8_t)pend;
-      if (pend == 0) src |= 1ull << k;
-    }
-    sm.val[c] = v;
-    sm.cv[c] = e;
-    sm.inm[c] = m;
-    pendb[c] = p;
-  }
-  __syncthreads();
-
-  int cur = -1;
-  for (;;) {
-    if (cur < 0) {
-      if (src == 0) break;
-      const int k = __builtin_ctzll(src);
-      src &= src - 1;
-      cur = tid + k * NT;
-    }
-    int nxt = -1;
-    const uint32_t e = sm.cv[cur];
-    if (e < 8) {
-      const int r = cur / TS, col = cur % TS;
-      const int tr = r + ddr(e), tc = col + ddc(e);
-      if (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) {
-        const int t = tr * TS + tc;
-        const uint32_t sh = 8 * (t & 3);
-        const uint32_t old = __hip_atomic_fetch_add(&sm.pend[t >> 2], (uint32_t)(0u - (1u << sh)), __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (((old >> sh) & 0xFF) == 1) {
-          df a = sm.val[t];
-          const uint32_t m = sm.inm[t];
+  V y[KPT];
 #pragma unroll
-          for (int i = 0; i < 8; ++i)
-            if (m & (1u << i)) a = df_add(a, sm.val[t + noff(i, TS)]);
-          sm.val[t] = a;
-          nxt = t;
-        }
-      }
+  for (int k = 0; k < KPT; ++k) {
+    const int i = tid + k * NT;
+    y[k] = Y[(i / TS + 1) * HS + i % TS + 1];
+  }
+  D8_STAMP(1, 3);
+  if constexpr (kCount) {
+    uint32_t* O = static_cast<uint32_t*>(out) + base;
+    uint32_t o[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int i = tid + k * NT;
+      o[k] = y[k] ? O[(i / TS) * W + i % TS] : 0u;
     }
-    cur = nxt;
-  }
-  __syncthreads();
-
-  bool cyc = false;
-  for (int k = 0; k < cpt; ++k) {
-    const int c = tid + k * NT;
-    if (c >= TS * TS) break;
-    if (pendb[c] != 0) cyc = true;
-  }
-  if (cyc) set_status(status, kStCycle);
-
-  if (FINAL) {
-    float* O = out + g.dm.off;
-    float* OL = out_lo ? out_lo + g.dm.off : nullptr;
-    for (int k = 0; k < cpt; ++k) {
-      const int c = tid + k * NT;
-      if (c >= TS * TS) break;
-      const int r = c / TS, col = c % TS;
-      if (r < g.th && col < g.tw) {
-        const df a = sm.val[c];
-        const float s = a.hi + a.lo;
-        O[(g.y0 + r) * W + g.x0 + col] = s;
-        if (OL) OL[(g.y0 + r) * W + g.x0 + col] = (a.hi - s) + a.lo;
-      }
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int i = tid + k * NT;
+      if (y[k]) O[(i / TS) * W + i % TS] = o[k] + y[k];
     }
   } else {
-    const int P = perim_count(g.tw, g.th);
-    const int64_t sb = g.tile * cap;
-    for (int j = tid; j < cap; j += NT) {
-      uint8_t ec = 0xFF;
-      if (j < P) {
-        int r, col;
-        perim_cell(j, g.tw, g.th, r, col);
-        const uint32_t k = sm.cv[r * TS + col];
-        if (k < 8) {
-          const int tr = r + ddr(k), tc = col + ddc(k);
-          if (!(tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw)) {
-            ec = (uint8_t)k;
-            ex_val[sb + j] = df_to_double(sm.val[r * TS + col]);
-          }
-        }
-        if (k != kNoData && ext_mask<TS>(sm.code, r, col, g)) {
-          int ur = r, uc = col, steps = 0;
-          uint16_t link = 0xFFFF;
-          for (;;) {
-            const uint32_t k2 = sm.cv[ur * TS + uc];
-            if (k2 >= 8) break;
-            const int tr = ur + ddr(k2), tc = uc + ddc(k2);
-            if (tr < 0 || tr >= g.th || tc < 0 || tc >= g.tw) {
-              link = (uint16_t)perim_slot(ur, uc, g.tw, g.th);
-              break;
-            }
-            ur = tr;
-            uc = tc;
-            if (++steps > g.tw * g.th) {
-              set_status(status, kStCycle);
-              break;
-            }
-          }
-          rl[sb + j] = link;
-        }
+    float* O = static_cast<float*>(out) + base;
+    float* L = out_lo ? out_lo + base : nullptr;
+    float o[KPT], l[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int i = tid + k * NT;
+      const int64_t q = (i / TS) * W + i % TS;
+      o[k] = y[k] != 0.0 ? O[q] : 0.0f;
+      l[k] = (L && y[k] != 0.0) ? L[q] : 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int i = tid + k * NT;
+      if (y[k] != 0.0) {
+        const int64_t q = (i / TS) * W + i % TS;
+        const double x = (double)o[k] + (double)l[k] + y[k];
+        const float hi = (float)x;
+        O[q] = hi;
+        if (L) L[q] = (float)(x - (double)hi);
       }
-      ex_code[sb + j] = ec;
     }
   }
+  D8_STAMP(1, 4);
+  D8_STAMP(1, 5);
 }
 
 // --------------------------------------------- backward: in-tile path sums --
@@ -1110,60 +868,6 @@ __device__ __forceinline__ void vadd(uint64_t* p, uint64_t v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 __device__ __forceinline__ void vadd(double* p, double v) { unsafeAtomicAdd(p, v); }
-
-// Forward: subtree sums F = (I - P)^-1 L over the exit forest by doubling,
-// F = (I + P)(I + P^2)(I + P^4)... L, where P^(2^j) adds a node's value into
-// its 2^j-th ancestor.  Three rotating value buffers (read / accumulate /
-// clear) and two ancestor buffers; round j stops early once no ancestors are
-// left, and records which buffer holds the result.
-template <typename V>
-__global__ void k_fres_init(DemTable tab, int ts, int cap, int64_t nslots, const uint8_t* __restrict__ ex_code,
-                            const uint16_t* __restrict__ rl, const V* __restrict__ ex_val, V* b0, V* b1, int32_t* a0,
-                            uint32_t* hdr) {
-  bool more = false;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t ec = ex_code[s];
-    if (ec >= 8) continue;
-    int64_t ts_;
-    int32_t par;
-    more |= exit_parent(tab, s, ts, cap, ec, rl, ts_, par);
-    a0[s] = par;
-    b0[s] = ex_val[s];
-    b1[s] = 0;
-  }
-  if (more) hdr[64] = 1;
-}
-
-template <typename V>
-__global__ void k_fres_round(int j, int64_t nslots, const uint8_t* __restrict__ ex_code, V* b0, V* b1, V* b2,
-                             int32_t* a0, int32_t* a1, uint32_t* hdr) {
-  if (hdr[64 + j] == 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && hdr[1] == 0xFFFFFFFFu) hdr[1] = (uint32_t)(j % 3);
-    return;
-  }
-  V* bufs[3] = {b0, b1, b2};
-  const V* cur = bufs[j % 3];
-  V* nxt = bufs[(j + 1) % 3];
-  V* clr = bufs[(j + 2) % 3];
-  const int32_t* ac = (j & 1) ? a1 : a0;
-  int32_t* an = (j & 1) ? a0 : a1;
-  bool more = false;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
-    if (ex_code[s] >= 8) continue;
-    const V v = cur[s];
-    vadd(&nxt[s], v);
-    const int32_t a = ac[s];
-    int32_t a2 = -1;
-    if (a >= 0) {
-      vadd(&nxt[a], v);
-      a2 = ac[a];
-    }
-    an[s] = a2;
-    clr[s] = 0;
-    more |= a2 >= 0;
-  }
-  if (more) hdr[64 + j + 1] = 1;
-}
 
 // ------------------------------------------------ super-block group pass --
 // The tile exits of a kSuper x kSuper super-block form a forest whose edges
@@ -1651,30 +1355,34 @@ hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, 
   return hipGetLastError();
 }
 
-hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_flowdirs, dim3((unsigned)nblocks), dim3(16, 16), 0, s, dem, dirs, tab);
-  return hipGetLastError();
-}
-
-template <int BW, int BH, int TS>
-static hipError_t count_blk(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
-  constexpr int NT = BW * BH / kDblCpt;
-  uint32_t* st = p.hdr;
-  // the final pass reads the full exit areas the resolve left in ex_val
-  const uint64_t* b0 = p.ex_val;
-  const uint64_t* b1 = p.ex_val;
-  const uint64_t* b2 = p.ex_val;
-  if (fin)
-    hipLaunchKernelGGL((k_block_count<BW, BH, TS, true>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, p.tab,
-                       p.nblocks, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
+hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s,
+                           bool steepest) {
+  if (steepest)
+    hipLaunchKernelGGL(k_flowdirs<true>, dim3((unsigned)nblocks), dim3(16, 16), 0, s, dem, dirs, tab);
   else
-    hipLaunchKernelGGL((k_block_count<BW, BH, TS, false>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, p.tab,
-                       p.nblocks, p.cap, p.ex_code, p.rl, p.ex_val, b0, b1, b2, p.hdr, out, st);
+    hipLaunchKernelGGL(k_flowdirs<false>, dim3((unsigned)nblocks), dim3(16, 16), 0, s, dem, dirs, tab);
   return hipGetLastError();
 }
 
-// Block shape of the count passes for a tile side and wave count (whole
-// tiles per block, 16 cells per thread).
+template <int BW, int BH, int TS, typename V>
+static hipError_t emit_blk(const Plan& p, const uint8_t* dirs, const float* w, void* out, float* out_lo,
+                           hipStream_t s) {
+  constexpr int NT = BW * BH / kDblCpt;
+  hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, w, p.tab,
+                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr);
+  return hipGetLastError();
+}
+
+template <int TS, typename V>
+static hipError_t fixup_ts(const Plan& p, const uint8_t* dirs, void* out, float* out_lo, hipStream_t s) {
+  // the full exit areas the resolve left in ex_val
+  hipLaunchKernelGGL((k_fixup<TS, V>), dim3((unsigned)p.ntiles), dim3(256), 0, s, dirs, p.tab, p.ntiles, p.cap,
+                     (const void*)p.ex_val, out, out_lo);
+  return hipGetLastError();
+}
+
+// Block shape of the emit pass for a tile side and wave count (whole tiles
+// per block, 16 cells per thread).
 void count_block_dims(int ts, int waves, int& bw, int& bh) {
   if (ts == 32) {
     bw = waves >= 2 ? 64 : 32;
@@ -1685,55 +1393,38 @@ void count_block_dims(int ts, int waves, int& bw, int& bh) {
   }
 }
 
-template <int TS>
-static hipError_t count_walk(const Plan& p, const uint8_t* dirs, bool fin, uint32_t* out, hipStream_t s) {
-  // the final pass reads the full exit areas the resolve left in ex_val
-  if (fin)
-    hipLaunchKernelGGL((k_walk_count<TS, true>), dim3((unsigned)p.ntiles), dim3(64), 0, s, dirs, p.tab, p.ntiles,
-                       p.cap, p.ex_code, p.rl, p.ex_val, p.ex_val, out, p.hdr);
-  else
-    hipLaunchKernelGGL((k_walk_count<TS, false>), dim3((unsigned)p.ntiles), dim3(64), 0, s, dirs, p.tab, p.ntiles,
-                       p.cap, p.ex_code, p.rl, p.ex_val, p.ex_val, out, p.hdr);
-  return hipGetLastError();
+template <typename V>
+static hipError_t tile_pass(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass, void* out,
+                            float* out_lo, hipStream_t s) {
+  constexpr bool kCount = std::is_same<V, uint32_t>::value;
+  if (final_pass) {
+    switch (p.ts) {
+      case 32: return fixup_ts<32, V>(p, dirs, out, out_lo, s);
+      case 64: return fixup_ts<64, V>(p, dirs, out, out_lo, s);
+      case 128:
+        if constexpr (kCount) return fixup_ts<128, V>(p, dirs, out, out_lo, s);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (p.ts == 32 && p.bw == 32 && p.bh == 32) return emit_blk<32, 32, 32, V>(p, dirs, w, out, out_lo, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 32) return emit_blk<64, 32, 32, V>(p, dirs, w, out, out_lo, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 64) return emit_blk<64, 64, 32, V>(p, dirs, w, out, out_lo, s);
+  if (p.ts == 64) return emit_blk<64, 64, 64, V>(p, dirs, w, out, out_lo, s);
+  if constexpr (kCount)
+    if (p.ts == 128) return emit_blk<128, 128, 128, V>(p, dirs, w, out, out_lo, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
                               hipStream_t s) {
   (void)nt;
-  if (p.walk && p.ts == 32) return count_walk<32>(p, dirs, final_pass, out, s);
-  if (p.walk && p.ts == 64) return count_walk<64>(p, dirs, final_pass, out, s);
-  if (p.ts == 32 && p.bw == 32 && p.bh == 32) return count_blk<32, 32, 32>(p, dirs, final_pass, out, s);
-  if (p.ts == 32 && p.bw == 64 && p.bh == 32) return count_blk<64, 32, 32>(p, dirs, final_pass, out, s);
-  if (p.ts == 32 && p.bw == 64 && p.bh == 64) return count_blk<64, 64, 32>(p, dirs, final_pass, out, s);
-  if (p.ts == 64) return count_blk<64, 64, 64>(p, dirs, final_pass, out, s);
-  if (p.ts == 128) return count_blk<128, 128, 128>(p, dirs, final_pass, out, s);
-  return hipErrorInvalidValue;
-}
-
-template <int TS>
-static hipError_t weighted_ts(const Plan& p, const uint8_t* dirs, const float* w, bool fin, float* out,
-                              float* out_lo, int nt, hipStream_t s) {
-  double* ev = reinterpret_cast<double*>(p.ex_val);
-  // the final pass reads the full exit areas the resolve left in ex_val
-  const double* b0 = ev;
-  const double* b1 = ev;
-  const double* b2 = ev;
-  if (fin)
-    hipLaunchKernelGGL((k_tile_weighted<TS, true>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, w, p.tab,
-                       p.ntiles, p.cap, p.ex_code, p.rl, ev, b0, b1, b2, p.hdr, out, out_lo, p.hdr);
-  else
-    hipLaunchKernelGGL((k_tile_weighted<TS, false>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, w, p.tab,
-                       p.ntiles, p.cap, p.ex_code, p.rl, ev, b0, b1, b2, p.hdr, out, out_lo, p.hdr);
-  return hipGetLastError();
+  return tile_pass<uint32_t>(p, dirs, nullptr, final_pass, out, nullptr, s);
 }
 
 hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass, float* out,
                                  float* out_lo, int nt, hipStream_t s) {
-  switch (p.ts) {
-    case 32: return weighted_ts<32>(p, dirs, w, final_pass, out, out_lo, nt, s);
-    case 64: return weighted_ts<64>(p, dirs, w, final_pass, out, out_lo, nt, s);
-  }
-  return hipErrorInvalidValue;
+  (void)nt;
+  return tile_pass<double>(p, dirs, w, final_pass, out, out_lo, s);
 }
 
 template <int TS>

@@ -1,0 +1,223 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py times
+(default tile and waves).
+
+Where the oracle finishes in seconds (8192^2 with NoData, 4096^2 weighted, the
+512-DEM batch) the GPU results are compared with it cell by cell.  At 32768^2
+and on the 16384^2 serpentine they are checked by properties that hold at any
+size and pin the result completely: on a D8 forest the recursion of Eq. (1),
+A(p) = w(p) + sum of A over the cells draining into p, has exactly one
+solution, so an exact integer check of it at every cell (done here with plain
+torch integer ops, independent of the library) proves the counts; the
+serpentine adds its closed forms; flow directions are compared with the
+oracle on sampled row bands.
+"""
+import numpy as np
+import pytest
+
+import demgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU machines too
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1605_05773_amd as d8  # noqa: E402
+from gpu_util import assert_rel, dev, to_dev, to_np  # noqa: E402
+
+DR = [0, -1, -1, -1, 0, 1, 1, 1]
+DC = [1, 1, 0, -1, -1, -1, 0, 1]
+
+
+def say(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+def identity_mismatches(dirs_t, A_t):
+    """Cells where A != [valid] + sum of A over the cells draining in (int64,
+    on the GPU with torch), plus NoData cells with A != 0."""
+    H, W = dirs_t.shape
+    A = A_t.to(torch.int64) if A_t.dtype != torch.uint32 else A_t.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    S = torch.zeros((H + 2, W + 2), dtype=torch.int64, device=A.device)
+    for k in range(8):
+        contrib = torch.where(dirs_t == k, A, torch.zeros((), dtype=torch.int64, device=A.device))
+        S[1 + DR[k]:H + 1 + DR[k], 1 + DC[k]:W + 1 + DC[k]] += contrib
+        del contrib
+    valid = (dirs_t != 255).to(torch.int64)
+    bad = (A != valid + S[1:H + 1, 1:W + 1]).sum().item()
+    del S
+    return bad, A
+
+
+def outlet_total(dirs_t, A64):
+    return A64[dirs_t == 8].sum().item()
+
+
+def rows_vs_oracle(z_t, dirs_t, nbands=4, rows=64, seed=0):
+    """Flow directions of sampled row bands against the oracle (a band plus a
+    one-row halo; its own first/last row are not compared)."""
+    H, W = z_t.shape
+    rng = np.random.default_rng(seed)
+    starts = [0, H - rows] + list(rng.integers(1, H - rows - 1, nbands))
+    for r0 in starts:
+        lo, hi = max(r0 - 1, 0), min(r0 + rows + 1, H)
+        zb = z_t[lo:hi].cpu().numpy()
+        ref = oracle.flowdirs(zb)
+        got = dirs_t[lo:hi].cpu().numpy()
+        a = 1 if lo > 0 else 0
+        b = (hi - lo) - (1 if hi < H else 0)
+        np.testing.assert_array_equal(got[a:b], ref[a:b], err_msg=f"band at row {r0}")
+
+
+# ------------------------------------------------------- 32768^2, one GPU
+
+def test_counts_32768_identity():
+    """The bench's size and configuration on a rough tilted surface with NoData
+    holes (every interior path meanders towards the north-west corner, so the
+    perimeter forest is as deep as the grid)."""
+    n = 32768
+    g = torch.Generator(device=dev()).manual_seed(2)
+    say("generating 32768^2 surface on the GPU")
+    y = torch.arange(n, device=dev(), dtype=torch.float32).view(n, 1)
+    x = torch.arange(n, device=dev(), dtype=torch.float32).view(1, n)
+    z = 0.01 * (x + y) + 0.008 * torch.rand((n, n), generator=g, device=dev())
+    z[torch.rand((n, n), generator=g, device=dev()) < 1e-4] = float("nan")
+    del x, y
+    dirs = d8.flowdirs(z)
+    torch.cuda.synchronize()
+    say("flow directions: sampled bands vs oracle")
+    rows_vs_oracle(z, dirs)
+    del z
+    say("accumulating")
+    A = d8.accum(dirs)
+    torch.cuda.synchronize()
+    assert d8.device_status() == d8.D8_OK
+    say("identity check")
+    bad, A64 = identity_mismatches(dirs, A)
+    assert bad == 0
+    assert outlet_total(dirs, A64) == (dirs != 255).sum().item()
+
+
+def test_counts_serpentine_16384_closed_forms():
+    n = 16384
+    say("serpentine 16384^2")
+    z = to_dev(demgen.serpentine_fast(n, n))
+    dirs = d8.flowdirs(z)
+    del z
+    A = d8.accum(dirs)
+    torch.cuda.synchronize()
+    assert d8.device_status() == d8.D8_OK
+    bad, A64 = identity_mismatches(dirs, A)
+    assert bad == 0
+    edge = torch.zeros((n, n), dtype=torch.bool, device=dev())
+    edge[0] = edge[-1] = True
+    edge[:, 0] = edge[:, -1] = True
+    assert A64.max().item() == n * n - (4 * n - 5)
+    assert (A64[edge] == 1).sum().item() == 4 * n - 5
+
+
+# ---------------------------------------------- 8192^2 with NoData (oracle)
+
+@pytest.fixture(scope="module")
+def c1():
+    z = demgen.config_dem("c1")
+    d = oracle.flowdirs(z)
+    return z, d
+
+
+def test_c1_flowdirs_and_counts_exact(c1):
+    z, d = c1
+    dd = d8.flowdirs(to_dev(z))
+    np.testing.assert_array_equal(to_np(dd), d)
+    got = to_np(d8.accum(dd))
+    assert d8.device_status() == d8.D8_OK
+    np.testing.assert_array_equal(got, oracle.accum_u32(d))
+
+
+def test_c1_weighted_and_backward(c1):
+    _, d = c1
+    w = demgen.lognormal_f32(d.shape, 303)
+    g = demgen.lognormal_f32(d.shape, 304)
+    dd = to_dev(d)
+    A = to_np(d8.accum(dd, to_dev(w)))
+    assert_rel(A, oracle.accum_f64(d, w), 1e-6, "c1 weighted")
+    G = to_np(d8.accum_backward(dd, to_dev(g)))
+    assert d8.device_status() == d8.D8_OK
+    assert_rel(G, oracle.backward_f64(d, g), 1e-6, "c1 backward")
+
+
+# ----------------------------------- 4096^2 weighted: gauges, targets, FD
+
+def test_c3_gauges_targets_and_finite_differences():
+    """Forward vs fp64; the gradient of L = sum over 64 gauges of (A - t)^2 vs
+    the fp64 adjoint; 32 central differences of L (exact for a quadratic, so
+    any step works; h = 1) on the fp64 oracle vs the GPU gradient."""
+    z = demgen.config_dem("c3")
+    d = oracle.flowdirs(z)
+    w = demgen.lognormal_f32(d.shape, 303)
+    xi = demgen.normal_f64(d.shape, 304)
+    Aw = oracle.accum_f64(d, w)
+    cnt = oracle.accum_u32(d)
+    rng = np.random.default_rng(305)
+    cand = np.flatnonzero(cnt.ravel() >= 1000)
+    gauges = rng.choice(cand, 64, replace=False)
+    t = oracle.accum_f64(d, (w.astype(np.float64) * np.exp(0.2 * xi)))
+    tg = t.ravel()[gauges]
+
+    dd = to_dev(d)
+    out = torch.empty(d.shape, dtype=torch.float32, device=dev())
+    lo = torch.empty(d.shape, dtype=torch.float32, device=dev())
+    d8.accum(dd, to_dev(w), out=out, out_lo=lo)
+    A_gpu = to_np(out)
+    assert_rel(A_gpu, Aw, 1e-6, "c3 forward")
+    # residuals from the double-float pair (the pair carries ~48 bits)
+    Ag = to_np(out).astype(np.float64).ravel()[gauges] + to_np(lo).astype(np.float64).ravel()[gauges]
+    resid = Ag - tg
+    gL = np.zeros(d.size, np.float64)
+    gL[gauges] = 2.0 * resid
+    g32 = gL.astype(np.float32).reshape(d.shape)
+    G_gpu = to_np(d8.accum_backward(dd, to_dev(g32)))
+    assert d8.device_status() == d8.D8_OK
+    G_ref = oracle.backward_f64(d, g32)
+    nz = G_ref != 0
+    assert (G_gpu[~nz] == 0).all()
+    assert_rel(G_gpu[nz], G_ref[nz], 1e-6, "c3 backward")
+
+    # finite differences on the fp64 oracle
+    def loss(wv):
+        a = oracle.accum_f64(d, wv).ravel()[gauges]
+        return float(((a - tg) ** 2).sum())
+
+    up = np.flatnonzero(G_ref.ravel() != 0)
+    fd_cells = np.random.default_rng(306).choice(up, 32, replace=False)
+    w64 = w.astype(np.float64)
+    for c in fd_cells:
+        wp = w64.copy()
+        wp.ravel()[c] += 1.0
+        wm = w64.copy()
+        wm.ravel()[c] -= 1.0
+        fd = (loss(wp) - loss(wm)) / 2.0
+        an = float(G_gpu.ravel()[c])
+        assert abs(an - fd) <= 1e-5 * abs(fd) + 1e-9, (c, an, fd)
+
+
+# ------------------------------------------------------ 512-DEM batch
+
+def test_c4_batch_vs_oracle():
+    say("generating the 512-DEM batch")
+    shapes, dems, ws, gs = demgen.c4_batch()
+    b = d8.Batch(shapes, dev())
+    dirs = [oracle.flowdirs(z) for z in dems]
+    dp = b.pack([to_dev(x) for x in dirs], torch.uint8)
+    wp = b.pack([to_dev(x) for x in ws], torch.float32)
+    gp = b.pack([to_dev(x) for x in gs], torch.float32)
+    say("batched calls")
+    C = b.unpack(d8.accum_batched(b, dp))
+    A = b.unpack(d8.accum_batched(b, dp, wp))
+    G = b.unpack(d8.accum_backward_batched(b, dp, gp))
+    assert d8.device_status() == d8.D8_OK
+    for i in range(len(shapes)):
+        np.testing.assert_array_equal(to_np(C[i]), oracle.accum_u32(dirs[i]), err_msg=f"dem {i}")
+        assert_rel(to_np(A[i]), oracle.accum_f64(dirs[i], ws[i]), 1e-6, f"batched weighted {i}")
+        assert_rel(to_np(G[i]), oracle.backward_f64(dirs[i], gs[i]), 1e-6, f"batched backward {i}")

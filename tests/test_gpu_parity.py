@@ -61,6 +61,27 @@ def test_flowdirs_c0_and_ties():
         np.testing.assert_array_equal(gpu_flowdirs(zp), oracle.flowdirs(zp))
 
 
+@pytest.mark.parametrize("shape,nan", [((1, 1), 0), ((3, 3), 0), ((70, 131), 0), ((129, 67), 0.2), ((300, 257), 0.02)])
+@pytest.mark.parametrize("seed", [0, 3])
+def test_flowdirs_steepest_random(shape, nan, seed):
+    z = random_dem(*shape, seed, nan)
+    np.testing.assert_array_equal(to_np(d8.flowdirs(to_dev(z), rule="steepest")), oracle.flowdirs(z, rule="steepest"))
+
+
+def test_flowdirs_steepest_planes_and_c0():
+    y, x = np.mgrid[0:40, 0:37].astype(np.float64)
+    for a, b in [(0.01, 0.004), (0.004, 0.01), (0.01, 0.0), (-0.01, 0.004), (0.003, -0.02)]:
+        z = (a * x + b * y).astype(np.float32)
+        np.testing.assert_array_equal(to_np(d8.flowdirs(to_dev(z), rule="steepest")),
+                                      oracle.flowdirs(z, rule="steepest"))
+    z = demgen.config_dem("c0")
+    d = oracle.flowdirs(z, rule="steepest")
+    dg = d8.flowdirs(to_dev(z), rule="steepest")
+    np.testing.assert_array_equal(to_np(dg), d)
+    assert (d != oracle.flowdirs(z)).any()  # the two rules differ on real terrain
+    np.testing.assert_array_equal(to_np(d8.accum(dg)), oracle.accum_u32(d))
+
+
 # ------------------------------------------------------------------- counts
 
 @pytest.mark.parametrize("tile", TILES)

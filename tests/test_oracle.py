@@ -322,3 +322,60 @@ def test_batch_shapes_ranges():
         lo, hi = min(r, c), max(r, c)
         assert 64 <= hi <= 2048 and lo >= 16
         assert lo == 16 or hi / lo <= 4.0 * (1 + 1.0 / lo)
+
+
+# ------------------------------------------------- steepest-slope rule (Sec. 3)
+# Slope to a neighbour = drop / distance, distance sqrt(2) for diagonals.  On
+# a plane z = a*x + b*y (a, b >= 0) the candidate slopes are W: a, N: b,
+# NW: (a + b)/sqrt(2), NE: (b - a)/sqrt(2), SW: (a - b)/sqrt(2); the expected
+# interior codes below follow from those by hand (margins >= 1 %).
+
+@pytest.mark.parametrize("a,b,lowest,steepest", [
+    (0.01, 0.004, 3, 4),    # NW lowest; W steeper (0.01 > 0.014/sqrt2 = 0.0099)
+    (0.004, 0.01, 3, 2),    # NW lowest; N steeper
+    (0.01, 0.01, 3, 3),     # NW both
+    (0.01, 0.0, 3, 4),      # lowest: NW/W/SW tie -> NW; steepest: W (0.01 > 0.0071)
+    (0.0, 0.01, 1, 2),      # lowest: NE/N/NW tie -> NE; steepest: N
+    (-0.01, 0.004, 1, 0),   # mirrored: NE lowest, E steeper
+])
+def test_steepest_vs_lowest_planes(a, b, lowest, steepest):
+    y, x = np.mgrid[0:20, 0:23].astype(np.float64)
+    z = (a * x + b * y).astype(np.float32)
+    lo = oracle.flowdirs(z)
+    st = oracle.flowdirs(z, rule="steepest")
+    assert (lo[1:-1, 1:-1] == lowest).all()
+    assert (st[1:-1, 1:-1] == steepest).all()
+    assert (st[0] == 8).all() and (st[:, 0] == 8).all() and (st[-1] == 8).all() and (st[:, -1] == 8).all()
+
+
+def test_steepest_plane_counts_closed_form():
+    # a = 0.01, b = 0.004: every interior cell drains W along its row, so an
+    # interior cell (r, c) collects the W - 1 - c cells from itself to column
+    # W - 2, and the west edge cell collects W - 1.
+    H, W = 17, 29
+    y, x = np.mgrid[0:H, 0:W].astype(np.float64)
+    d = oracle.flowdirs((0.01 * x + 0.004 * y).astype(np.float32), rule="steepest")
+    A = oracle.accum_u32(d)
+    for r in range(1, H - 1):
+        np.testing.assert_array_equal(A[r, 1:W - 1], W - 1 - np.arange(1, W - 1))
+        assert A[r, 0] == W - 1 and A[r, W - 1] == 1
+    assert (A[0] == 1).all() and (A[-1] == 1).all()
+
+
+def test_steepest_hand_cases():
+    # Centre 10.0 of a 5x5 block (border 100 keeps the other cells out of the
+    # way).  Case 1: E drops 1.0 (slope 1.0), NE drops 1.3 (slope 0.919):
+    # lowest -> NE (1), steepest -> E (0).  Case 2: no lower neighbour -> 8.
+    # Case 3: E and W both drop 1.0 -> first in order: E.  Case 4: NE drops
+    # 1.5 (1.0607) beats E 1.0 under both rules.
+    def block(e, ne, w=100.0):
+        z = np.full((5, 5), 100.0, np.float32)
+        z[2, 2] = 10.0
+        z[2, 3] = e
+        z[1, 3] = ne
+        z[2, 1] = w
+        return z
+    for z, lo, st in [(block(9.0, 8.7), 1, 0), (block(11.0, 12.0), 8, 8), (block(9.0, 50.0, 9.0), 0, 0),
+                      (block(9.0, 8.5), 1, 1)]:
+        assert oracle.flowdirs(z)[2, 2] == lo
+        assert oracle.flowdirs(z, rule="steepest")[2, 2] == st
