@@ -109,40 +109,6 @@ __device__ __forceinline__ DemInfo dem_of_tile(const DemTable& t, int64_t tile) 
   return t.dev[lo];
 }
 
-// ----------------------------------------------------------- double-float --
-// A value is the unevaluated sum hi + lo of two float32 numbers.  Additions
-// use Knuth's TwoSum (an error-free transformation) followed by Dekker's
-// Fast2Sum renormalisation; no multiplications, so contraction cannot change
-// them.
-struct df {
-  float hi, lo;
-};
-
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-__device__ __forceinline__ void fast_two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  e = b - (s - a);
-}
-__device__ __forceinline__ df df_add(df a, df b) {
-  float s, e;
-  two_sum(a.hi, b.hi, s, e);
-  e += a.lo + b.lo;
-  df r;
-  fast_two_sum(s, e, r.hi, r.lo);
-  return r;
-}
-__device__ __forceinline__ df df_from_double(double x) {
-  df r;
-  r.hi = (float)x;
-  r.lo = (float)(x - (double)r.hi);
-  return r;
-}
-__device__ __forceinline__ double df_to_double(df a) { return (double)a.hi + (double)a.lo; }
-
 __device__ __forceinline__ void set_status(uint32_t* st, uint32_t bit) {
   __hip_atomic_fetch_or(st, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -247,32 +247,6 @@ __device__ __forceinline__ void load_halo(uint8_t* code, const uint8_t* __restri
   }
 }
 
-template <int TS>
-__device__ __forceinline__ void load_codes(uint8_t* code, const uint8_t* __restrict__ dirs, const TileGeo& g) {
-  load_halo<TS, TS>(code, dirs, g.dm, g.y0, g.x0, g.tw);
-}
-
-// Validated code of in-tile cell (r, c): 0..7 (drains to a valid cell), 8
-// (outlet, or an invalid code / target, which also raises the status word).
-template <int TS>
-__device__ __forceinline__ uint8_t eff_code(const uint8_t* code, int r, int c, const TileGeo& g,
-                                            uint32_t* status) {
-  constexpr int HS = TS + 2;
-  const uint8_t k = code[(r + 1) * HS + c + 1];
-  if (k == kNone) return kNone;
-  if (k > kNone) {
-    set_status(status, kStBadDir);
-    return kNone;
-  }
-  const int tr = r + ddr(k), tc = c + ddc(k);
-  const int64_t gy = g.y0 + tr, gx = g.x0 + tc;
-  if (gy < 0 || gy >= g.dm.H || gx < 0 || gx >= g.dm.W || code[(tr + 1) * HS + tc + 1] == kNoData) {
-    set_status(status, kStBadDir);
-    return kNone;
-  }
-  return k;
-}
-
 // Masks of the inputs of in-tile cell (r, c): bit i set if the neighbour at
 // offset i drains into the cell; split into inputs inside the tile and inputs
 // from outside it (receivers).  Branch-free.
@@ -318,16 +292,26 @@ __device__ __forceinline__ uint32_t ext_mask(const uint8_t* code, int r, int c, 
 
 // Sum of the resolved areas of the exits (in other tiles) that drain into
 // receiver (r, c): the inflow the paper's master returns for a receiver.
+// A cell has at most 5 outside neighbours (a tile corner); all loads are
+// issued before the first is used.
 template <typename V>
 __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext, int r, int c, const TileGeo& g,
                                            int ts, int cap) {
-  V x = 0;
-  for (int i = 0; i < 8; ++i) {
-    if (ext & (1u << i)) {
-      const int64_t gy = g.y0 + r + ddr(i), gx = g.x0 + c + ddc(i);
-      x += F[slot_of_cell(g.dm, gy, gx, ts, cap)];
-    }
+  int64_t sl[5];
+  uint32_t m = ext;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t i = m ? (uint32_t)__builtin_ctz(m) : 0u;
+    const int64_t gy = g.y0 + r + ddr(i), gx = g.x0 + c + ddc(i);
+    sl[k] = m ? slot_of_cell(g.dm, gy, gx, ts, cap) : -1;
+    m &= m - 1;
   }
+  V t[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) t[k] = F[sl[k] >= 0 ? sl[k] : 0];
+  V x = 0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) x += sl[k] >= 0 ? t[k] : (V)0;
   return x;
 }
 
@@ -444,6 +428,26 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
     sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
   }
   __syncthreads();
+  if constexpr (kCount) {
+    // Counts: rake the leaves first.  A cell with no in-tile input holds its
+    // final value (1) already; adding it to its target once takes it out of
+    // every doubling round (a third of the cells on real terrain).  In-tile
+    // inputs are counted in the high half of the value word (values stay
+    // below 2^16: TS <= 128); the high half is dropped at the end.  A raked
+    // cell keeps its target in the root field; its root is its target's.
+#pragma unroll
+    for (int k = 0; k < kDblCpt; ++k)
+      if (a[k] != kNoAnc) atomicAdd(&sm.val[a[k]], 1u << 16);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kDblCpt; ++k) {
+      if (a[k] != kNoAnc && (sm.val[tid + k * NT] >> 16) == 0) {
+        atomicAdd(&sm.val[a[k]], 1u);
+        a[k] = kNoAnc;
+      }
+    }
+    __syncthreads();
+  }
   D8_STAMP(0, 2);
 
   // Doubling rounds.  Reads of a round (own value, ancestor's link word) all
@@ -483,6 +487,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
   D8_STAMP(0, 3);
 
   // Tile-local areas.
+  constexpr uint32_t kValMask16 = 0xFFFFu;
 #pragma unroll
   for (int k = 0; k < kDblCpt; ++k) {
     const int c = tid + k * NT;
@@ -490,7 +495,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
     if (r < g.bh && col < g.bw) {
       const int64_t o = base + r * W + col;
       if constexpr (kCount) {
-        static_cast<uint32_t*>(out)[o] = sm.val[c];
+        static_cast<uint32_t*>(out)[o] = sm.val[c] & kValMask16;
       } else {
         const double x = sm.val[c];
         const float hi = (float)x;
@@ -522,14 +527,18 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
           if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
               sm.code[(r + 1 + ddr_t(code)) * HS + col + 1 + ddc_t(code)] != kNoData) {
             ec = (uint8_t)code;
-            static_cast<EV*>(ex_val)[sb + j] = (EV)sm.val[r * BW + col];
+            if constexpr (kCount)
+              static_cast<EV*>(ex_val)[sb + j] = (EV)(sm.val[r * BW + col] & kValMask16);
+            else
+              static_cast<EV*>(ex_val)[sb + j] = (EV)sm.val[r * BW + col];
           }
         }
       }
       if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
         // Receiver: the root of its in-tile path is the exit it leaves by,
-        // unless the path ends at an outlet.
-        const int root = (int)(sm.link[r * BW + col] >> 16);
+        // unless the path ends at an outlet.  (One more hop: a raked cell's
+        // root field holds its target; a root's holds itself.)
+        const int root = (int)(sm.link[sm.link[r * BW + col] >> 16] >> 16);
         const int R = root / BW, C = root % BW;
         const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
         uint16_t link = 0xFFFF;
@@ -704,140 +713,168 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
 }
 
 // --------------------------------------------- backward: in-tile path sums --
-// G(c) = g(c) + G(target(c)).  Inside a tile this is a path sum to the tile's
-// root, computed by pointer jumping (each round doubles the covered path
-// length); S, the pointer and the root label are updated through registers
-// between barriers.  Deterministic.
-constexpr uint16_t kEnd = 0xFFFF;
-constexpr int kBwdMaxCpt = 16;
-
-template <int TS>
-struct BSmem {
-  df S[TS * TS];
-  uint16_t ptr[TS * TS];
-  uint16_t lab[TS * TS];
-  uint8_t cv[TS * TS];
-  uint8_t code[(TS + 2) * (TS + 2)];
+// The adjoint of Eq. (1): G(c) = g(c) + G(target(c)).  Inside a tile this is
+// the sum of g along c's path to the tile root, computed by pointer jumping
+// (pull form, no atomics): in round j a cell adds the partial sum of its
+// 2^j-th ancestor and jumps to that ancestor's ancestor.  fp64 partial sums in
+// a fixed order, so the result is deterministic.  Block and link layout as in
+// k_block_emit (the saturating root field ends at the tile root).
+//   emit pass   writes, for every receiver, its path sum (rg) and the exit it
+//               leaves by (rl), and marks exits in ex_code;
+//   final pass  recomputes the path sums and adds H(root exit), the resolved
+//               path sum beyond the tile (0 for a path ending at an outlet).
+template <int BW, int BH>
+struct BwdSmem {
+  double S[BW * BH];
+  uint32_t link[BW * BH];
+  uint8_t code[(BW + 2) * (BH + 2)];
 };
 
-template <int TS, bool FINAL>
-__global__ __launch_bounds__(1024) void k_tile_backward(const uint8_t* __restrict__ dirs,
-                                                        const float* __restrict__ gin, DemTable tab, int64_t ntiles,
-                                                        int cap, uint8_t* __restrict__ ex_code,
-                                                        uint16_t* __restrict__ rl, double* __restrict__ rg,
-                                                        const double* __restrict__ H0, const double* __restrict__ H1,
-                                                        const uint32_t* __restrict__ hdr, float* __restrict__ out,
-                                                        uint32_t* __restrict__ status) {
-  __shared__ BSmem<TS> sm;
-  constexpr int HS = TS + 2;
-  const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
-  const int NT = blockDim.x, tid = threadIdx.x;
-  const int cpt = (TS * TS + NT - 1) / NT;
-  load_codes<TS>(sm.code, dirs, g);
-  __syncthreads();
-  const float* G = gin + g.dm.off;
+template <int BW, int BH, int TS, bool FINAL>
+__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
+    const uint8_t* __restrict__ dirs, const float* __restrict__ gin, DemTable tab, int64_t nblocks, int cap,
+    uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, double* __restrict__ rg,
+    const double* __restrict__ H0, const double* __restrict__ H1, const uint32_t* __restrict__ hdr,
+    float* __restrict__ out, uint32_t* __restrict__ status) {
+  constexpr int NC = BW * BH;
+  constexpr int NT = NC / kDblCpt;
+  constexpr int HS = BW + 2;
+  constexpr int TPX = BW / TS, TPY = BH / TS;
+  static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
+  __shared__ BwdSmem<BW, BH> sm;
+  const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
+  const int tid = threadIdx.x;
   const int64_t W = g.dm.W;
-  for (int k = 0; k < cpt; ++k) {
+  const int64_t base = g.dm.off + g.y0 * W + g.x0;
+  double s[kDblCpt];
+#pragma unroll
+  for (int k = 0; k < kDblCpt; ++k) {
     const int c = tid + k * NT;
-    if (c >= TS * TS) break;
-    const int r = c / TS, col = c % TS;
-    df s = {0.0f, 0.0f};
-    uint16_t p = kEnd, lb = kEnd;
-    uint8_t e = kNoData;
-    if (r < g.th && col < g.tw && sm.code[(r + 1) * HS + col + 1] != kNoData) {
-      e = eff_code<TS>(sm.code, r, col, g, status);
-      s.hi = G[(g.y0 + r) * W + g.x0 + col];
-      lb = (uint16_t)c;
-      if (e < 8) {
-        const int tr = r + ddr(e), tc = col + ddc(e);
-        if (tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw) {
-          p = (uint16_t)(tr * TS + tc);
-          lb = kEnd;
-        }
-      }
-    }
-    sm.S[c] = s;
-    sm.ptr[c] = p;
-    sm.lab[c] = lb;
-    sm.cv[c] = e;
+    const int r = c / BW, col = c % BW;
+    s[k] = (r < g.bh && col < g.bw) ? (double)gin[base + r * W + col] : 0.0;
+  }
+  load_halo<BW, BH, NT>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
+  __syncthreads();
+
+  const bool border = g.y0 == 0 || g.x0 == 0 || g.y0 + BH >= g.dm.H || g.x0 + BW >= g.dm.W;
+  uint16_t a[kDblCpt];
+#pragma unroll
+  for (int k = 0; k < kDblCpt; ++k) {
+    const int c = tid + k * NT;
+    const int r = c / BW, col = c % BW;
+    const uint32_t code = sm.code[(r + 1) * HS + col + 1];
+    const bool ok = r < g.bh && col < g.bw && code != kNoData;
+    const uint32_t d = code & 7u;
+    const int dr = ddr_t(d), dc = ddc_t(d);
+    const int ta = r / TS, tb = col / TS;
+    const int th = min(TS, g.bh - ta * TS), tw = min(TS, g.bw - tb * TS);
+    const int tr = r - ta * TS + dr, tc = col - tb * TS + dc;
+    const bool drains = ok && code < 8u;
+    const bool inside = drains && tr >= 0 && tr < th && tc >= 0 && tc < tw;
+    const uint8_t tcode = sm.code[(r + 1 + dr) * HS + col + 1 + dc];
+    bool bad = ok && (code > 8u || (drains && tcode == kNoData));
+    if (border)
+      bad |= drains && !inside &&
+             (g.y0 + r + dr < 0 || g.y0 + r + dr >= g.dm.H || g.x0 + col + dc < 0 || g.x0 + col + dc >= g.dm.W);
+    if (bad) set_status(status, kStBadDir);
+    a[k] = (inside && tcode != kNoData) ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
+    if (!ok) s[k] = 0.0;
+    sm.S[c] = s[k];
+    sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
   }
   __syncthreads();
 
-  const int lim = TS * TS * 2;  // a cycle never converges; stop after enough rounds
+  const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
   for (int round = 0;; ++round) {
-    df ns[kBwdMaxCpt];
-    uint16_t np[kBwdMaxCpt], nl[kBwdMaxCpt];
-    bool any = false;
+    double sa[kDblCpt];
+    uint32_t nl[kDblCpt];
 #pragma unroll
-    for (int k = 0; k < kBwdMaxCpt; ++k) {
-      const int c = tid + k * NT;
-      np[k] = kEnd;
-      if (k < cpt && c < TS * TS) {
-        const uint16_t p = sm.ptr[c];
-        if (p != kEnd) {
-          ns[k] = df_add(sm.S[c], sm.S[p]);
-          np[k] = sm.ptr[p];
-          nl[k] = sm.lab[p];
-          any = true;
-        }
+    for (int k = 0; k < kDblCpt; ++k) {
+      if (a[k] != kNoAnc) {
+        sa[k] = sm.S[a[k]];
+        nl[k] = sm.link[a[k]];
       }
     }
     __syncthreads();
+    bool more = false;
 #pragma unroll
-    for (int k = 0; k < kBwdMaxCpt; ++k) {
-      const int c = tid + k * NT;
-      if (k < cpt && c < TS * TS && sm.ptr[c] != kEnd) {
-        sm.S[c] = ns[k];
-        sm.ptr[c] = np[k];
-        sm.lab[c] = nl[k];
+    for (int k = 0; k < kDblCpt; ++k) {
+      if (a[k] != kNoAnc) {
+        const int c = tid + k * NT;
+        s[k] += sa[k];
+        sm.S[c] = s[k];
+        const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
+        const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
+        a[k] = na;
+        sm.link[c] = (uint32_t)na | (root << 16);
+        more |= na != kNoAnc;
       }
     }
-    if (!__syncthreads_or(any)) break;
-    if ((1 << min(round, 30)) > lim) {
+    if (!__syncthreads_or(more)) break;
+    if (round >= max_rounds) {
       set_status(status, kStCycle);
       break;
     }
   }
   __syncthreads();
 
+  // Slot of the exit at block cell `root` if that cell is an exit of its
+  // tile, else -1.
+  auto exit_slot = [&](int root, int64_t& sl) -> bool {
+    const int R = root / BW, C = root % BW;
+    const int ta = R / TS, tb = C / TS;
+    const int thc = min(TS, g.bh - ta * TS), twc = min(TS, g.bw - tb * TS);
+    const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
+    if (k2 >= 8u) return false;
+    const int tr = R - ta * TS + ddr_t(k2), tc = C - tb * TS + ddc_t(k2);
+    if (tr >= 0 && tr < thc && tc >= 0 && tc < twc) return false;  // not an exit
+    const int64_t gy = g.y0 + R + ddr_t(k2), gx = g.x0 + C + ddc_t(k2);
+    if (gy < 0 || gy >= g.dm.H || gx < 0 || gx >= g.dm.W ||
+        sm.code[(R + 1 + ddr_t(k2)) * HS + C + 1 + ddc_t(k2)] == kNoData)
+      return false;
+    sl = (g.dm.tile0 + (g.ty0 + ta) * g.dm.TX + g.tx0 + tb) * cap +
+         perim_slot(R - ta * TS, C - tb * TS, twc, thc);
+    return true;
+  };
+
   if (FINAL) {
-    const uint32_t fi = hdr[2];
-    const double* Hb = fi == 0 ? H0 : H1;
-    float* O = out + g.dm.off;
-    const int64_t sb = g.tile * cap;
-    for (int k = 0; k < cpt; ++k) {
+    const double* Hb = hdr[2] == 0 ? H0 : H1;
+#pragma unroll
+    for (int k = 0; k < kDblCpt; ++k) {
       const int c = tid + k * NT;
-      if (c >= TS * TS) break;
-      const int r = c / TS, col = c % TS;
-      if (r < g.th && col < g.tw) {
-        double acc = df_to_double(sm.S[c]);
-        const uint16_t root = sm.lab[c];
-        if (sm.cv[c] != kNoData && root != kEnd && sm.cv[root] < 8) {
-          acc += Hb[sb + perim_slot(root / TS, root % TS, g.tw, g.th)];
+      const int r = c / BW, col = c % BW;
+      if (r < g.bh && col < g.bw) {
+        double x = s[k];
+        if (sm.code[(r + 1) * HS + col + 1] != kNoData) {
+          int64_t sl;
+          if (exit_slot((int)(sm.link[c] >> 16), sl)) x += Hb[sl];
         }
-        O[(g.y0 + r) * W + g.x0 + col] = (float)acc;
+        out[base + r * W + col] = (float)x;
       }
     }
   } else {
-    const int P = perim_count(g.tw, g.th);
-    const int64_t sb = g.tile * cap;
-    for (int j = tid; j < cap; j += NT) {
+    for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
+      const int tl = idx / cap, j = idx - tl * cap;
+      const int ta = tl / TPX, tb = tl - ta * TPX;
+      const int th = g.bh - ta * TS, tw = g.bw - tb * TS;
+      if (th <= 0 || tw <= 0) continue;
+      const int thc = min(TS, th), twc = min(TS, tw);
+      const int64_t sb = (g.dm.tile0 + (g.ty0 + ta) * g.dm.TX + g.tx0 + tb) * cap;
       uint8_t ec = 0xFF;
-      if (j < P) {
-        int r, col;
-        perim_cell(j, g.tw, g.th, r, col);
-        const int c = r * TS + col;
-        const uint32_t k = sm.cv[c];
-        if (k < 8) {
-          const int tr = r + ddr(k), tc = col + ddc(k);
-          if (!(tr >= 0 && tr < g.th && tc >= 0 && tc < g.tw)) ec = (uint8_t)k;
-        }
-        if (k != kNoData && ext_mask<TS>(sm.code, r, col, g)) {
-          const uint16_t root = sm.lab[c];
+      if (j < perim_count(twc, thc)) {
+        int lr, lc;
+        perim_cell(j, twc, thc, lr, lc);
+        const int r = ta * TS + lr, col = tb * TS + lc;
+        const int c = r * BW + col;
+        const uint32_t code = sm.code[(r + 1) * HS + col + 1];
+        int64_t sl;
+        if (code < 8u && exit_slot(c, sl)) ec = (uint8_t)code;
+        if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
           uint16_t link = 0xFFFF;
-          if (root != kEnd && sm.cv[root] < 8) link = (uint16_t)perim_slot(root / TS, root % TS, g.tw, g.th);
+          const int root = (int)(sm.link[c] >> 16);
+          if (exit_slot(root, sl)) link = (uint16_t)(sl - sb);
           rl[sb + j] = link;
-          rg[sb + j] = df_to_double(sm.S[c]);
+          rg[sb + j] = sm.S[c];
         }
       }
       ex_code[sb + j] = ec;
@@ -1108,7 +1145,7 @@ constexpr int kL2Shift = 40;
 constexpr uint64_t kL2One = 1ull << kL2Shift;
 constexpr uint64_t kL2Mask = kL2One - 1;
 constexpr uint32_t kL2HasKids = 0x80000000u;
-constexpr int kL2Steps = 64;
+constexpr int kL2Steps = 32;
 
 // Parent ids: -1 root; <= -2 a parked node (parent -(p + 2)).
 template <typename V>
@@ -1176,7 +1213,9 @@ __global__ void k_l2_prep(int32_t* anc, V* val, V* d0, V* d1, const uint64_t* pe
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t pa = anc[i];
     int32_t a = -1;
-    if (pa <= -2) {
+    if constexpr (!std::is_same<V, uint64_t>::value) {
+      a = pa;  // weighted: no stage 1 ran, every node takes part
+    } else if (pa <= -2) {
       a = -pa - 2;
     } else {
       bool unfinished;
@@ -1427,27 +1466,28 @@ hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float
   return tile_pass<double>(p, dirs, w, final_pass, out, out_lo, s);
 }
 
-template <int TS>
-static hipError_t backward_ts(const Plan& p, const uint8_t* dirs, const float* g, bool fin, float* out, int nt,
-                              hipStream_t s) {
+template <int BW, int BH, int TS>
+static hipError_t bwd_blk(const Plan& p, const uint8_t* dirs, const float* g, bool fin, float* out, hipStream_t s) {
+  constexpr int NT = BW * BH / kDblCpt;
   const double* b0 = reinterpret_cast<const double*>(p.buf[0]);
   const double* b1 = reinterpret_cast<const double*>(p.buf[1]);
   double* ev = reinterpret_cast<double*>(p.ex_val);
   if (fin)
-    hipLaunchKernelGGL((k_tile_backward<TS, true>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, g, p.tab,
-                       p.ntiles, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, true>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g, p.tab,
+                       p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
   else
-    hipLaunchKernelGGL((k_tile_backward<TS, false>), dim3((unsigned)p.ntiles), dim3(nt), 0, s, dirs, g, p.tab,
-                       p.ntiles, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, false>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g, p.tab,
+                       p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
   return hipGetLastError();
 }
 
 hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float* g, bool final_pass, float* out,
                                  int nt, hipStream_t s) {
-  switch (p.ts) {
-    case 32: return backward_ts<32>(p, dirs, g, final_pass, out, nt, s);
-    case 64: return backward_ts<64>(p, dirs, g, final_pass, out, nt, s);
-  }
+  (void)nt;
+  if (p.ts == 32 && p.bw == 32 && p.bh == 32) return bwd_blk<32, 32, 32>(p, dirs, g, final_pass, out, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 32) return bwd_blk<64, 32, 32>(p, dirs, g, final_pass, out, s);
+  if (p.ts == 32 && p.bw == 64 && p.bh == 64) return bwd_blk<64, 64, 32>(p, dirs, g, final_pass, out, s);
+  if (p.ts == 64) return bwd_blk<64, 64, 64>(p, dirs, g, final_pass, out, s);
   return hipErrorInvalidValue;
 }
 
@@ -1475,19 +1515,25 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
   V* b0 = reinterpret_cast<V*>(p.buf[0]);
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   V* b2 = reinterpret_cast<V*>(p.buf[2]);
-  // nodes: at most one per super-block perimeter cell
-  const unsigned g = grid_for(std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper), 256);
+  // Nodes: at most one per super-block perimeter cell.  One thread per node
+  // for the single passes (their work is a chain of dependent random
+  // accesses); the rounds loop over the nodes with a capped grid.
+  const int64_t maxn = std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper);
+  const unsigned gn = (unsigned)std::max<int64_t>(1, (maxn + 255) / 256);
+  const unsigned g = (unsigned)std::min<int64_t>(gn, 16384);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
   group_pass<LV, V, false>(p, s);
   uint64_t* pend = p.buf[2];
-  const unsigned gn = (unsigned)std::max<int64_t>(1, (std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper) + 255) / 256);
-  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
-  hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
-  hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_init<V>), dim3(gn), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
+  // Counts only: the weighted stage 1 would need a fence between its two
+  // atomics (an L2 write-back on this GPU) per step; doubling does it all.
+  if constexpr (std::is_same<V, uint64_t>::value)
+    hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_prep<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
   for (int j = 0; j < p.rounds; ++j)
     hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, p.hdr);
   hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
-  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, p.hdr);
+  hipLaunchKernelGGL((k_l2_fold<V>), dim3(gn), dim3(256), 0, s, b0, b1, b2, p.hdr);
   group_pass<LV, V, true>(p, s);
   return hipGetLastError();
 }
