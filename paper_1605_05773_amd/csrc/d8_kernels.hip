@@ -428,26 +428,6 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
     sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
   }
   __syncthreads();
-  if constexpr (kCount) {
-    // Counts: rake the leaves first.  A cell with no in-tile input holds its
-    // final value (1) already; adding it to its target once takes it out of
-    // every doubling round (a third of the cells on real terrain).  In-tile
-    // inputs are counted in the high half of the value word (values stay
-    // below 2^16: TS <= 128); the high half is dropped at the end.  A raked
-    // cell keeps its target in the root field; its root is its target's.
-#pragma unroll
-    for (int k = 0; k < kDblCpt; ++k)
-      if (a[k] != kNoAnc) atomicAdd(&sm.val[a[k]], 1u << 16);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
-      if (a[k] != kNoAnc && (sm.val[tid + k * NT] >> 16) == 0) {
-        atomicAdd(&sm.val[a[k]], 1u);
-        a[k] = kNoAnc;
-      }
-    }
-    __syncthreads();
-  }
   D8_STAMP(0, 2);
 
   // Doubling rounds.  Reads of a round (own value, ancestor's link word) all
@@ -487,7 +467,6 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
   D8_STAMP(0, 3);
 
   // Tile-local areas.
-  constexpr uint32_t kValMask16 = 0xFFFFu;
 #pragma unroll
   for (int k = 0; k < kDblCpt; ++k) {
     const int c = tid + k * NT;
@@ -495,7 +474,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
     if (r < g.bh && col < g.bw) {
       const int64_t o = base + r * W + col;
       if constexpr (kCount) {
-        static_cast<uint32_t*>(out)[o] = sm.val[c] & kValMask16;
+        static_cast<uint32_t*>(out)[o] = sm.val[c];
       } else {
         const double x = sm.val[c];
         const float hi = (float)x;
@@ -527,18 +506,14 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
           if (gy >= 0 && gy < g.dm.H && gx >= 0 && gx < g.dm.W &&
               sm.code[(r + 1 + ddr_t(code)) * HS + col + 1 + ddc_t(code)] != kNoData) {
             ec = (uint8_t)code;
-            if constexpr (kCount)
-              static_cast<EV*>(ex_val)[sb + j] = (EV)(sm.val[r * BW + col] & kValMask16);
-            else
-              static_cast<EV*>(ex_val)[sb + j] = (EV)sm.val[r * BW + col];
+            static_cast<EV*>(ex_val)[sb + j] = (EV)sm.val[r * BW + col];
           }
         }
       }
       if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
         // Receiver: the root of its in-tile path is the exit it leaves by,
-        // unless the path ends at an outlet.  (One more hop: a raked cell's
-        // root field holds its target; a root's holds itself.)
-        const int root = (int)(sm.link[sm.link[r * BW + col] >> 16] >> 16);
+        // unless the path ends at an outlet.
+        const int root = (int)(sm.link[r * BW + col] >> 16);
         const int R = root / BW, C = root % BW;
         const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
         uint16_t link = 0xFFFF;
@@ -576,8 +551,9 @@ __device__ __forceinline__ int hoff(uint32_t d) {
 
 // ------------------------------------------------------- finalising pass --
 // Alg. 7-8: each receiver's incoming area (the resolved areas of the exits of
-// other tiles that drain into it) is added to every cell on its downstream
-// path inside the tile.  The emit pass already wrote the tile-local areas, so
+// other tiles that drain into it, summed per receiver slot by the down pass of
+// the super-block resolve) is added to every cell on its downstream path
+// inside the tile.  The emit pass already wrote the tile-local areas, so
 // only the cells downstream of receivers change: each receiver with inflow
 // walks its path accumulating into an LDS array (paths may share cells; the
 // sums are exact for counts and fp64 for weights), then the touched cells of
@@ -596,12 +572,8 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   const int tid = threadIdx.x;
   const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
   D8_STAMP(1, 0);
-  load_halo<TS, TS, NT>(code, dirs, g.dm, g.y0, g.x0, g.tw);
-  for (int i = tid; i < NH; i += NT) Y[i] = 0;
-  if (tid == 0) any = 0;
-  __syncthreads();
-  // Inflow of every receiver (from the original halo codes).
-  const FV* Fv = static_cast<const FV*>(F);
+  // Inflow of every receiver slot, resolved by the super-block pass.
+  const FV* X = static_cast<const FV*>(F) + g.tile * cap;
   const int np = perim_count(g.tw, g.th);
   V xr[NRX];
   int hr[NRX];
@@ -613,16 +585,13 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
     if (j < np) {
       int lr, lc;
       perim_cell(j, g.tw, g.th, lr, lc);
-      const int h = (lr + 1) * HS + lc + 1;
-      if (code[h] != kNoData) {
-        const uint32_t ext = input_mask<TS>(code, lr, lc) & outside_dirs(lr, lc, g.tw, g.th);
-        if (ext) {
-          xr[q] = (V)gather_inflow<FV>(Fv, ext, lr, lc, g, TS, cap);
-          hr[q] = h;
-        }
-      }
+      xr[q] = (V)X[j];
+      hr[q] = (lr + 1) * HS + lc + 1;
     }
   }
+  load_halo<TS, TS, NT>(code, dirs, g.dm, g.y0, g.x0, g.tw);
+  for (int i = tid; i < NH; i += NT) Y[i] = 0;
+  if (tid == 0) any = 0;
   __syncthreads();
   // Fence the tile: the halo ring becomes kOutside, so a walk stops where its
   // path leaves the tile (cells beyond the DEM already hold kOutside).
@@ -940,7 +909,8 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
                                                V* __restrict__ l2val, int32_t* __restrict__ sbroot,
                                                int32_t* __restrict__ l2par, V* __restrict__ l2acc,
                                                uint64_t* __restrict__ l2pend, const V* __restrict__ F,
-                                               uint32_t* __restrict__ hdr, uint32_t* __restrict__ status) {
+                                               V* __restrict__ xin, uint32_t* __restrict__ hdr,
+                                               uint32_t* __restrict__ status) {
   using D = GroupDims<TS, LV>;
   constexpr int G = D::G, CAP = D::CAP, NN = D::NN, NT = D::NT, NPT = D::NPT;
   __shared__ LV val[NN];
@@ -957,12 +927,14 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   const int sbw = (int)min((int64_t)kSuper, (int64_t)dm.W - x0);
 
   uint16_t a[NPT];
-  int32_t tg[NPT];  // super-block exits: the tile exit the target receiver leads to
+  int32_t tg[NPT];   // super-block exits: the tile exit the target receiver leads to
+  uint16_t tin[NPT];  // exits inside the super-block: the node of their target receiver
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tid + k * NT;
     a[k] = kNoAnc;
     tg[k] = -1;
+    tin[k] = kNoAnc;
     if (n >= NN) continue;
     const int tl = n / CAP, j = n - tl * CAP;
     const int ta = tl / G, tb = tl - ta * G;
@@ -985,9 +957,12 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
       const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
       const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
       const int64_t tbase = (dm.tile0 + tty * dm.TX + ttx) * CAP;
-      const uint16_t lk = rl[tbase + perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth)];
+      const int rs = perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth);
+      const uint16_t lk = rl[tbase + rs];
       if (gy >= y0 && gy < y0 + sbh && gx >= x0 && gx < x0 + sbw) {
-        if (lk != 0xFFFF) a[k] = (uint16_t)(((tty - ty0) * G + (ttx - tx0)) * CAP + lk);
+        const int tnode = (int)(((tty - ty0) * G + (ttx - tx0)) * CAP);
+        if (lk != 0xFFFF) a[k] = (uint16_t)(tnode + lk);
+        tin[k] = (uint16_t)(tnode + rs);
       } else {
         f |= 2;
         // super-block exit: remember the tile exit its target receiver leads
@@ -1001,11 +976,19 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
     flag[n] = f;
   }
   __syncthreads();
+  constexpr int NPB = (4 * kSuper - 4 + NT - 1) / NT;  // super-block perimeter cells per thread
+  V xb[NPB];
+  int nb[NPB];
   if (DOWN) {
     // Resolved inflow of every receiver on the super-block's border, added at
     // the tile exit its in-tile path leaves by.
     const int P = perim_count(sbw, sbh);
-    for (int i = tid; i < P; i += NT) {
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      const int i = tid + q * NT;
+      xb[q] = 0;
+      nb[q] = -1;
+      if (i >= P) continue;
       int r, c;
       perim_cell(i, sbw, sbh, r, c);
       const int64_t gy = y0 + r, gx = x0 + c;
@@ -1024,8 +1007,12 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
         const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
         const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
         const int64_t tbase = (dm.tile0 + tty * dm.TX + ttx) * CAP;
-        const uint16_t lk = rl[tbase + perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth)];
-        if (lk != 0xFFFF) ladd(&val[((tty - ty0) * G + (ttx - tx0)) * CAP + lk], (LV)x);
+        const int rs = perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth);
+        const uint16_t lk = rl[tbase + rs];
+        const int tnode = (int)(((tty - ty0) * G + (ttx - tx0)) * CAP);
+        if (lk != 0xFFFF) ladd(&val[tnode + lk], (LV)x);
+        xb[q] = x;
+        nb[q] = tnode + rs;
       }
     }
     __syncthreads();
@@ -1064,14 +1051,42 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   __syncthreads();
 
   if (DOWN) {
+    // Full areas of the tile exits, then the inflow of every receiver slot of
+    // the super-block's tiles (Alg. 7's incoming area): the exits inside the
+    // super-block that drain into it plus, on the border, the resolved exits
+    // of neighbouring super-blocks.  The finalising pass reads these inflows.
+    LV vv[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int n = tid + k * NT;
-      if (n < NN && (flag[n] & 1)) {
+      const bool act = n < NN && (flag[n] & 1);
+      vv[k] = act ? val[n] : (LV)0;
+      if (act) {
         const int tl = n / CAP, j = n - tl * CAP;
         const int ta = tl / G, tb = tl - ta * G;
-        ex_val[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (V)val[n];
+        ex_val[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (V)vv[k];
       }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (tid + k * NT < NN) val[tid + k * NT] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (tin[k] != kNoAnc && vv[k] != (LV)0) ladd(&val[tin[k]], vv[k]);
+#pragma unroll
+    for (int q = 0; q < NPB; ++q)
+      if (nb[q] >= 0) ladd(&val[nb[q]], (LV)xb[q]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int n = tid + k * NT;
+      if (n >= NN) continue;
+      const int tl = n / CAP, j = n - tl * CAP;
+      const int ta = tl / G, tb = tl - ta * G;
+      if (ty0 + ta < dm.TY && tx0 + tb < dm.TX)
+        xin[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (V)val[n];
     }
     return;
   }
@@ -1414,9 +1429,9 @@ static hipError_t emit_blk(const Plan& p, const uint8_t* dirs, const float* w, v
 
 template <int TS, typename V>
 static hipError_t fixup_ts(const Plan& p, const uint8_t* dirs, void* out, float* out_lo, hipStream_t s) {
-  // the full exit areas the resolve left in ex_val
+  // the receiver inflows the super-block pass left in buf[2]
   hipLaunchKernelGGL((k_fixup<TS, V>), dim3((unsigned)p.ntiles), dim3(256), 0, s, dirs, p.tab, p.ntiles, p.cap,
-                     (const void*)p.ex_val, out, out_lo);
+                     (const void*)p.buf[2], out, out_lo);
   return hipGetLastError();
 }
 
@@ -1498,7 +1513,7 @@ static void group_launch(const Plan& p, hipStream_t s) {
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   uint64_t* b2 = p.buf[2];
   hipLaunchKernelGGL((k_group<TS, LV, V, DOWN>), dim3((unsigned)p.nsb), dim3(512), 0, s, p.tab, p.nsb, p.ex_code,
-                     p.rl, ev, b0, p.anc[1], p.anc[0], b1, b2, b0, p.hdr, p.hdr);
+                     p.rl, ev, b0, p.anc[1], p.anc[0], b1, b2, b0, reinterpret_cast<V*>(b2), p.hdr, p.hdr);
 }
 
 template <typename LV, typename V, bool DOWN>
