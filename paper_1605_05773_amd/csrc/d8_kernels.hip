@@ -589,6 +589,23 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
       hr[q] = (lr + 1) * HS + lc + 1;
     }
   }
+  constexpr int KPT = NC / NT;
+  static_assert(KPT * NT == NC, "whole tile per pass");
+  const int64_t base = g.dm.off + g.y0 * g.dm.W + g.x0;
+  const int64_t W = g.dm.W;
+  using OV = std::conditional_t<kCount, uint32_t, float>;
+  OV o[KPT];
+  float l[KPT];
+  {
+    const OV* O = static_cast<const OV*>(out) + base;
+#pragma unroll
+    for (int k = 0; k < KPT; ++k) {
+      const int i = tid + k * NT;
+      const bool in = i / TS < g.th && i % TS < g.tw;
+      o[k] = in ? O[(i / TS) * W + i % TS] : (OV)0;
+      l[k] = (!kCount && out_lo && in) ? out_lo[base + (i / TS) * W + i % TS] : 0.0f;
+    }
+  }
   load_halo<TS, TS, NT>(code, dirs, g.dm, g.y0, g.x0, g.tw);
   for (int i = tid; i < NH; i += NT) Y[i] = 0;
   if (tid == 0) any = 0;
@@ -628,12 +645,8 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
     D8_STAMP(1, 5);
     return;
   }
-  // All loads of a thread are issued before any store (the stores could
-  // otherwise alias the next loads and serialise them).
-  constexpr int KPT = NC / NT;
-  static_assert(KPT * NT == NC, "whole tile per pass");
-  const int64_t base = g.dm.off + g.y0 * g.dm.W + g.x0;
-  const int64_t W = g.dm.W;
+  // The tile-local values written by the emit pass were fetched at the start
+  // (their latency overlaps the walks); only the touched cells are stored.
   V y[KPT];
 #pragma unroll
   for (int k = 0; k < KPT; ++k) {
@@ -643,12 +656,6 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   D8_STAMP(1, 3);
   if constexpr (kCount) {
     uint32_t* O = static_cast<uint32_t*>(out) + base;
-    uint32_t o[KPT];
-#pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const int i = tid + k * NT;
-      o[k] = y[k] ? O[(i / TS) * W + i % TS] : 0u;
-    }
 #pragma unroll
     for (int k = 0; k < KPT; ++k) {
       const int i = tid + k * NT;
@@ -657,14 +664,6 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   } else {
     float* O = static_cast<float*>(out) + base;
     float* L = out_lo ? out_lo + base : nullptr;
-    float o[KPT], l[KPT];
-#pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const int i = tid + k * NT;
-      const int64_t q = (i / TS) * W + i % TS;
-      o[k] = y[k] != 0.0 ? O[q] : 0.0f;
-      l[k] = (L && y[k] != 0.0) ? L[q] : 0.0f;
-    }
 #pragma unroll
     for (int k = 0; k < KPT; ++k) {
       const int i = tid + k * NT;
