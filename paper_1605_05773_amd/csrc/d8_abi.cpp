@@ -96,6 +96,11 @@ static DemInfo single_dem(int64_t rows, int64_t cols, int ts, int waves = 0) {
 
 static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves) {
   count_block_dims(p.ts, waves, p.bw, p.bh);
+  // 64 x 64 tiles: waves 2 / 4 / 8 / 16 -> 32 / 16 / 8 / 4 cells per thread
+  // (default 8: 512 threads)
+  p.cpt = 16;
+  if (p.bw == 64 && p.bh == 64 && p.ts == 64)
+    p.cpt = waves == 2 ? 32 : (waves == 4 ? 16 : (waves == 16 ? 4 : 8));
   p.nblocks = 0;
   p.nsb = 0;
   if (hd) {

@@ -33,7 +33,8 @@ struct Plan {
   int64_t ntiles = 0;
   int64_t nslots = 0;
   int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
-  int bw = 0, bh = 0;  // workgroup block of the count passes (whole tiles)
+  int bw = 0, bh = 0;  // workgroup block of the tile passes (whole tiles)
+  int cpt = 16;        // cells per thread of the tile passes
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes

@@ -326,7 +326,6 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
 // close to their tile root drop out early; integer sums make the result
 // independent of the order of the atomic additions.
 constexpr uint16_t kNoAnc = 0xFFFF;
-constexpr int kDblCpt = 16;  // cells per thread
 
 // Per cell: value, and a link word (low 16 bits: the exact 2^j-th in-tile
 // ancestor or kNoAnc; high 16 bits: the ancestor at distance
@@ -366,15 +365,15 @@ __device__ __forceinline__ BlockGeo block_geo(const DemTable& tab, int64_t blk) 
 // (fp64 sums: the rounding of any order is far below float32 output
 // precision).  The pass writes the tile-local areas to the output and the
 // perimeter records of every tile; the finalising pass adds the inflows.
-template <int BW, int BH, int TS, typename V>
-__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
+template <int BW, int BH, int TS, typename V, int CPT>
+__global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
     const uint8_t* __restrict__ dirs, const float* __restrict__ w, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, void* __restrict__ ex_val, void* __restrict__ out,
     float* __restrict__ out_lo, uint32_t* __restrict__ status) {
   constexpr bool kCount = std::is_same<V, uint32_t>::value;
   using EV = std::conditional_t<kCount, uint64_t, double>;  // exit values for the resolve
   constexpr int NC = BW * BH;
-  constexpr int NT = NC / kDblCpt;
+  constexpr int NT = NC / CPT;
   constexpr int HS = BW + 2;
   constexpr int TPX = BW / TS, TPY = BH / TS;  // tiles per block row / column
   static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
@@ -384,10 +383,10 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
   const int64_t W = g.dm.W;
   const int64_t base = g.dm.off + g.y0 * W + g.x0;  // the block's first cell
   D8_STAMP(0, 0);
-  float wv[kCount ? 1 : kDblCpt];
+  float wv[kCount ? 1 : CPT];
   if (!kCount) {
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       const int c = tid + k * NT;
       const int r = c / BW, col = c % BW;
       wv[k] = (w && r < g.bh && col < g.bw) ? w[base + r * W + col] : 1.0f;
@@ -400,9 +399,9 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
   // Setup: in-tile target (ancestor at distance 1) and initial value.  Only
   // blocks on the DEM's border can have targets off the grid.
   const bool border = g.y0 == 0 || g.x0 == 0 || g.y0 + BH >= g.dm.H || g.x0 + BW >= g.dm.W;
-  uint16_t a[kDblCpt];
+  uint16_t a[CPT];
 #pragma unroll
-  for (int k = 0; k < kDblCpt; ++k) {
+  for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NT;
     const int r = c / BW, col = c % BW;
     const uint32_t code = sm.code[(r + 1) * HS + col + 1];
@@ -435,10 +434,10 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
   // becomes the ancestor's saturating pointer when the exact one runs out.
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
   for (int round = 0;; ++round) {
-    V v[kDblCpt];
-    uint32_t nl[kDblCpt];
+    V v[CPT];
+    uint32_t nl[CPT];
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
         v[k] = sm.val[tid + k * NT];
         nl[k] = sm.link[a[k]];
@@ -447,7 +446,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
     __syncthreads();
     bool more = false;
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
         atomicAdd(&sm.val[a[k]], v[k]);
         const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
@@ -468,7 +467,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_emit(
 
   // Tile-local areas.
 #pragma unroll
-  for (int k = 0; k < kDblCpt; ++k) {
+  for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NT;
     const int r = c / BW, col = c % BW;
     if (r < g.bh && col < g.bw) {
@@ -698,14 +697,14 @@ struct BwdSmem {
   uint8_t code[(BW + 2) * (BH + 2)];
 };
 
-template <int BW, int BH, int TS, bool FINAL>
-__global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
+template <int BW, int BH, int TS, bool FINAL, int CPT>
+__global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
     const uint8_t* __restrict__ dirs, const float* __restrict__ gin, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, double* __restrict__ rg,
     const double* __restrict__ H0, const double* __restrict__ H1, const uint32_t* __restrict__ hdr,
     float* __restrict__ out, uint32_t* __restrict__ status) {
   constexpr int NC = BW * BH;
-  constexpr int NT = NC / kDblCpt;
+  constexpr int NT = NC / CPT;
   constexpr int HS = BW + 2;
   constexpr int TPX = BW / TS, TPY = BH / TS;
   static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
@@ -714,9 +713,9 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
   const int tid = threadIdx.x;
   const int64_t W = g.dm.W;
   const int64_t base = g.dm.off + g.y0 * W + g.x0;
-  double s[kDblCpt];
+  double s[CPT];
 #pragma unroll
-  for (int k = 0; k < kDblCpt; ++k) {
+  for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NT;
     const int r = c / BW, col = c % BW;
     s[k] = (r < g.bh && col < g.bw) ? (double)gin[base + r * W + col] : 0.0;
@@ -725,9 +724,9 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
   __syncthreads();
 
   const bool border = g.y0 == 0 || g.x0 == 0 || g.y0 + BH >= g.dm.H || g.x0 + BW >= g.dm.W;
-  uint16_t a[kDblCpt];
+  uint16_t a[CPT];
 #pragma unroll
-  for (int k = 0; k < kDblCpt; ++k) {
+  for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NT;
     const int r = c / BW, col = c % BW;
     const uint32_t code = sm.code[(r + 1) * HS + col + 1];
@@ -754,10 +753,10 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
 
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
   for (int round = 0;; ++round) {
-    double sa[kDblCpt];
-    uint32_t nl[kDblCpt];
+    double sa[CPT];
+    uint32_t nl[CPT];
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
         sa[k] = sm.S[a[k]];
         nl[k] = sm.link[a[k]];
@@ -766,7 +765,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
     __syncthreads();
     bool more = false;
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
         const int c = tid + k * NT;
         s[k] += sa[k];
@@ -808,7 +807,7 @@ __global__ __launch_bounds__(BW * BH / kDblCpt) void k_block_bwd(
   if (FINAL) {
     const double* Hb = hdr[2] == 0 ? H0 : H1;
 #pragma unroll
-    for (int k = 0; k < kDblCpt; ++k) {
+    for (int k = 0; k < CPT; ++k) {
       const int c = tid + k * NT;
       const int r = c / BW, col = c % BW;
       if (r < g.bh && col < g.bw) {
@@ -1417,13 +1416,26 @@ hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab,
   return hipGetLastError();
 }
 
+template <int BW, int BH, int TS, typename V, int CPT>
+static hipError_t emit_cpt(const Plan& p, const uint8_t* dirs, const float* w, void* out, float* out_lo,
+                           hipStream_t s) {
+  constexpr int NT = BW * BH / CPT;
+  hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, w, p.tab,
+                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr);
+  return hipGetLastError();
+}
+
+// Cells per thread of the block passes: 16, or for a 64 x 64 block of one
+// tile 4, 8 or 32 (1024, 512 or 128 threads).
 template <int BW, int BH, int TS, typename V>
 static hipError_t emit_blk(const Plan& p, const uint8_t* dirs, const float* w, void* out, float* out_lo,
                            hipStream_t s) {
-  constexpr int NT = BW * BH / kDblCpt;
-  hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, w, p.tab,
-                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr);
-  return hipGetLastError();
+  if constexpr (BW == 64 && BH == 64) {
+    if (p.cpt == 4) return emit_cpt<BW, BH, TS, V, 4>(p, dirs, w, out, out_lo, s);
+    if (p.cpt == 8) return emit_cpt<BW, BH, TS, V, 8>(p, dirs, w, out, out_lo, s);
+    if (p.cpt == 32) return emit_cpt<BW, BH, TS, V, 32>(p, dirs, w, out, out_lo, s);
+  }
+  return emit_cpt<BW, BH, TS, V, 16>(p, dirs, w, out, out_lo, s);
 }
 
 template <int TS, typename V>
@@ -1480,19 +1492,29 @@ hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float
   return tile_pass<double>(p, dirs, w, final_pass, out, out_lo, s);
 }
 
-template <int BW, int BH, int TS>
-static hipError_t bwd_blk(const Plan& p, const uint8_t* dirs, const float* g, bool fin, float* out, hipStream_t s) {
-  constexpr int NT = BW * BH / kDblCpt;
+template <int BW, int BH, int TS, int CPT>
+static hipError_t bwd_cpt(const Plan& p, const uint8_t* dirs, const float* g, bool fin, float* out, hipStream_t s) {
+  constexpr int NT = BW * BH / CPT;
   const double* b0 = reinterpret_cast<const double*>(p.buf[0]);
   const double* b1 = reinterpret_cast<const double*>(p.buf[1]);
   double* ev = reinterpret_cast<double*>(p.ex_val);
   if (fin)
-    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, true>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g, p.tab,
-                       p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, true, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g,
+                       p.tab, p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
   else
-    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, false>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g, p.tab,
-                       p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, false, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g,
+                       p.tab, p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
   return hipGetLastError();
+}
+
+template <int BW, int BH, int TS>
+static hipError_t bwd_blk(const Plan& p, const uint8_t* dirs, const float* g, bool fin, float* out, hipStream_t s) {
+  if constexpr (BW == 64 && BH == 64) {
+    if (p.cpt == 4) return bwd_cpt<BW, BH, TS, 4>(p, dirs, g, fin, out, s);
+    if (p.cpt == 8) return bwd_cpt<BW, BH, TS, 8>(p, dirs, g, fin, out, s);
+    if (p.cpt == 32) return bwd_cpt<BW, BH, TS, 32>(p, dirs, g, fin, out, s);
+  }
+  return bwd_cpt<BW, BH, TS, 16>(p, dirs, g, fin, out, s);
 }
 
 hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float* g, bool final_pass, float* out,

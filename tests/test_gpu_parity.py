@@ -313,7 +313,7 @@ def test_batched_matches_single(tile, waves):
 
 # ------------------------------------------- every tile / waves configuration
 
-CONFIGS = [(32, 1), (32, 2), (32, 4), (64, 1), (64, 2), (64, 4), (64, 8), (128, 8), (128, 16)]
+CONFIGS = [(32, 1), (32, 2), (32, 4), (64, 1), (64, 2), (64, 4), (64, 8), (64, 16), (128, 8), (128, 16)]
 
 
 @pytest.fixture(scope="module")
