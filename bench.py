@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
+    ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (profiler calibration of byte counters)")
     args = ap.parse_args()
@@ -126,7 +127,6 @@ def main():
     dem = torch.from_numpy(np.ascontiguousarray(z)).to(dev)
     dirs = d8.flowdirs(dem)
     torch.cuda.synchronize()
-    del dem
     out = torch.empty((H, W), dtype=torch.uint32, device=dev)
     ws = d8.workspace(d8.workspace_bytes(H, W, args.tile), dev)
     stream = torch.cuda.current_stream(dev)
@@ -183,6 +183,32 @@ def main():
 
     extra = {"phase_ms": phase_ms, "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
              "op_bytes_per_cell": OP_BYTES_PER_CELL, "wall_s": round(wall, 3)}
+
+    if not args.no_fused:
+        # End to end from the DEM: d8_flowdirs + d8_accum vs the fused
+        # d8_accum_dem (codes computed inside the tile pass).
+        dtmp = torch.empty_like(dirs)
+        for _ in range(2):
+            d8.accum_dem(dem, tile=args.tile, out=out, dirs=dtmp, ws=ws)
+        torch.cuda.synchronize()
+        f0, f1, f2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        f0.record(stream)
+        for _ in range(args.steps):
+            d8.flowdirs(dem)
+            d8.accum(dirs, tile=args.tile, out=out, ws=ws)
+        f1.record(stream)
+        for _ in range(args.steps):
+            d8.accum_dem(dem, tile=args.tile, out=out, dirs=dtmp, ws=ws)
+        f2.record(stream)
+        torch.cuda.synchronize()
+        sep = f0.elapsed_time(f1) / args.steps
+        fus = f1.elapsed_time(f2) / args.steps
+        extra["dem_to_counts"] = {"separate_ms": round(sep, 4), "fused_ms": round(fus, 4),
+                                  "fused_gcells": round(H * W / fus / 1e6, 2),
+                                  "separate_gcells": round(H * W / sep / 1e6, 2)}
+        log(f"DEM -> counts: {extra['dem_to_counts']}")
+        del dtmp
+    del dem
 
     if not args.no_fwdbwd:
         # Forward vs forward+backward of the differentiable weighted form on the

@@ -122,6 +122,16 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
  * dL/dA = grad_out the gradient is grad_weights = (I - P)^-T grad_out:
  * grad_weights(c) = sum of grad_out over the cells on c's downstream path,
  * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0. */
+/* Fused flow directions and counts: dem (float32, NaN = NoData) -> dirs and
+ * out, equal to d8_flowdirs followed by d8_accum with unit weights and
+ * D8_U32 output.  The tile pass computes each tile's codes from the DEM
+ * (with a two-cell halo) instead of reading a direction field, so one read
+ * of the DEM replaces d8_flowdirs' read and write and the tile pass' read of
+ * the codes.  dirs (uint8 [rows*cols], output) receives the codes.  Same
+ * workspace, tile and error rules as d8_accum. */
+d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, uint32_t* out, void* ws,
+                       size_t ws_bytes, int tile, void* stream);
+
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
 

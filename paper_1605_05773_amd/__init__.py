@@ -55,6 +55,7 @@ def lib():
             "d8_workspace_bytes": ([I64, I64, I32], SZ),
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
+            "d8_accum_dem": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
             "d8_batched_workspace_bytes": ([P, I32, I32], SZ),
             "d8_flowdirs_batched": ([P, P, P, I32, P, P, SZ, P], I32),
             "d8_accum_batched": ([P, P, P, I32, P, I32, P, P, P, SZ, I32, I32, P], I32),
@@ -75,8 +76,8 @@ def lib():
 
 
 EXPORTED = (
-    "d8_flowdirs", "d8_flowdirs_steepest", "d8_workspace_bytes", "d8_accum", "d8_accum_backward", "d8_batched_workspace_bytes",
-    "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
+    "d8_flowdirs", "d8_flowdirs_steepest", "d8_workspace_bytes", "d8_accum", "d8_accum_dem", "d8_accum_backward",
+    "d8_batched_workspace_bytes", "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
 )
 NPHASES = 10
@@ -165,6 +166,23 @@ def accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, *, tile: int 
                           tile, _stream(dirs.device)), "d8_accum")
     _maybe_debug_check(ws, dirs.device)
     return out
+
+
+def accum_dem(dem: torch.Tensor, *, tile: int = 0, out: torch.Tensor | None = None,
+              dirs: torch.Tensor | None = None, ws: torch.Tensor | None = None):
+    """Fused flow directions + counts of a float32 DEM: returns (counts uint32,
+    dirs uint8), equal to accum(flowdirs(dem))."""
+    dem = _dev_tensor(dem, torch.float32, "dem")
+    if dem.dim() != 2:
+        raise ValueError("dem must be 2-D")
+    H, W = dem.shape
+    out = torch.empty((H, W), dtype=torch.uint32, device=dem.device) if out is None else out
+    dirs = torch.empty((H, W), dtype=torch.uint8, device=dem.device) if dirs is None else dirs
+    nb = workspace_bytes(H, W, tile)
+    ws = workspace(nb, dem.device) if ws is None else ws
+    _check(lib().d8_accum_dem(dem.data_ptr(), H, W, dirs.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), tile,
+                              _stream(dem.device)), "d8_accum_dem")
+    return out, dirs
 
 
 def accum_backward(dirs: torch.Tensor, grad_out: torch.Tensor, *, tile: int = 0,

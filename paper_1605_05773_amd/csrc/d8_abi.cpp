@@ -315,6 +315,16 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
   return run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, (hipStream_t)stream);
 }
 
+d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, uint32_t* out, void* ws,
+                       size_t ws_bytes, int tile, void* stream) {
+  if (!dem || !dirs || !out) return D8_EINVAL;
+  Plan p;
+  d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
+  if (st != D8_OK) return st;
+  p.dem = dem;  // the emit pass computes (and writes) the codes
+  return run_forward(p, dirs, nullptr, D8_U32, out, nullptr, 0, (hipStream_t)stream);
+}
+
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream) {
   if (!dirs || !grad_out || !grad_weights) return D8_EINVAL;

@@ -35,6 +35,7 @@ struct Plan {
   int rounds = 0;    // resolve rounds (ceil(log2(nslots+1)) + 1)
   int bw = 0, bh = 0;  // workgroup block of the tile passes (whole tiles)
   int cpt = 16;        // cells per thread of the tile passes
+  const float* dem = nullptr;  // fused call: codes computed from this DEM in the emit pass
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes

@@ -333,10 +333,63 @@ constexpr uint16_t kNoAnc = 0xFFFF;
 // ancestor has run out).
 template <int BW, int BH, typename V>
 struct DblSmem {
-  V val[BW * BH];
-  uint32_t link[BW * BH];
+  union {
+    struct {
+      V val[BW * BH];
+      uint32_t link[BW * BH];
+    };
+    float z[(BW + 4) * (BH + 4)];  // fused call: the DEM block with a 2-cell halo
+  };
   uint8_t code[(BW + 2) * (BH + 2)];
 };
+
+// Fused call: D8 codes of the block and its 1-cell halo computed from the DEM
+// (same rule as k_flowdirs) into `code`; the block's own codes are written to
+// `dirs` for the finalising pass.  Cells beyond the DEM get kOutside.
+template <int BW, int BH, int NT, typename SM>
+__device__ __forceinline__ void codes_from_dem(SM& sm, const float* __restrict__ dem, uint8_t* __restrict__ dirs,
+                                               const DemInfo& dm, int64_t y0, int64_t x0) {
+  constexpr int ZS = BW + 4, ZN = (BW + 4) * (BH + 4);
+  constexpr int HS = BW + 2, HN = (BW + 2) * (BH + 2);
+  const int tid = threadIdx.x;
+  const int64_t H = dm.H, W = dm.W;
+  const float* Z = dem + dm.off;
+  const float kNaN = __builtin_nanf("");
+  for (int i = tid; i < ZN; i += NT) {
+    const int lr = i / ZS, lc = i - lr * ZS;
+    const int64_t gy = y0 + lr - 2, gx = x0 + lc - 2;
+    sm.z[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? Z[gy * W + gx] : kNaN;
+  }
+  __syncthreads();
+  for (int i = tid; i < HN; i += NT) {
+    const int lr = i / HS, lc = i - lr * HS;
+    const int64_t gy = y0 + lr - 1, gx = x0 + lc - 1;
+    uint8_t k = kOutside;
+    if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      const float* p = &sm.z[(lr + 1) * ZS + lc + 1];
+      const float c = p[0];
+      if (__builtin_isnan(c)) {
+        k = kNoData;
+      } else if (gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1) {
+        k = kNone;
+      } else {
+        const float n0 = p[1], n1 = p[1 - ZS], n2 = p[-ZS], n3 = p[-1 - ZS];
+        const float n4 = p[-1], n5 = p[ZS - 1], n6 = p[ZS], n7 = p[ZS + 1];
+        const bool nanadj = __builtin_isnan(n0) | __builtin_isnan(n1) | __builtin_isnan(n2) |
+                            __builtin_isnan(n3) | __builtin_isnan(n4) | __builtin_isnan(n5) |
+                            __builtin_isnan(n6) | __builtin_isnan(n7);
+        k = nanadj ? kNone : lowest8(c, n0, n1, n2, n3, n4, n5, n6, n7);
+      }
+    }
+    sm.code[i] = k;
+  }
+  __syncthreads();
+  uint8_t* D = dirs + dm.off;
+  for (int i = tid; i < BW * BH; i += NT) {
+    const int r = i / BW, c = i - r * BW;
+    if (y0 + r < H && x0 + c < W) D[(y0 + r) * W + x0 + c] = sm.code[(r + 1) * HS + c + 1];
+  }
+}
 
 struct BlockGeo {
   DemInfo dm;
@@ -369,7 +422,8 @@ template <int BW, int BH, int TS, typename V, int CPT>
 __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
     const uint8_t* __restrict__ dirs, const float* __restrict__ w, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, void* __restrict__ ex_val, void* __restrict__ out,
-    float* __restrict__ out_lo, uint32_t* __restrict__ status) {
+    float* __restrict__ out_lo, uint32_t* __restrict__ status, const float* __restrict__ dem,
+    uint8_t* __restrict__ dirs_out) {
   constexpr bool kCount = std::is_same<V, uint32_t>::value;
   using EV = std::conditional_t<kCount, uint64_t, double>;  // exit values for the resolve
   constexpr int NC = BW * BH;
@@ -392,8 +446,12 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
       wv[k] = (w && r < g.bh && col < g.bw) ? w[base + r * W + col] : 1.0f;
     }
   }
-  load_halo<BW, BH, NT>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
-  __syncthreads();
+  if (dem) {
+    codes_from_dem<BW, BH, NT>(sm, dem, dirs_out, g.dm, g.y0, g.x0);
+  } else {
+    load_halo<BW, BH, NT>(sm.code, dirs, g.dm, g.y0, g.x0, g.bw);
+    __syncthreads();
+  }
   D8_STAMP(0, 1);
 
   // Setup: in-tile target (ancestor at distance 1) and initial value.  Only
@@ -1421,7 +1479,8 @@ static hipError_t emit_cpt(const Plan& p, const uint8_t* dirs, const float* w, v
                            hipStream_t s) {
   constexpr int NT = BW * BH / CPT;
   hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, w, p.tab,
-                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr);
+                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr, p.dem,
+                     const_cast<uint8_t*>(dirs));
   return hipGetLastError();
 }
 

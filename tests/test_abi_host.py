@@ -66,6 +66,8 @@ def test_argument_errors_before_device_work():
     assert L.d8_flowdirs(None, 10, 10, fake, None) == d8.D8_EINVAL
     assert L.d8_flowdirs(fake, 1 << 20, 1 << 13, fake, None) == d8.D8_EINVAL
     assert L.d8_flowdirs_steepest(None, 10, 10, fake, None) == d8.D8_EINVAL
+    assert L.d8_accum_dem(None, 10, 10, fake, fake, fake, 1 << 20, 0, None) == d8.D8_EINVAL
+    assert L.d8_accum_dem(fake, 10, 10, None, fake, fake, 1 << 20, 0, None) == d8.D8_EINVAL
     assert L.d8_flowdirs_steepest(fake, 0, 10, fake, None) == d8.D8_EINVAL
     assert L.d8_device_status(None, None, None) == d8.D8_EINVAL
 

@@ -88,7 +88,6 @@ def test_counts_32768_identity():
     torch.cuda.synchronize()
     say("flow directions: sampled bands vs oracle")
     rows_vs_oracle(z, dirs)
-    del z
     say("accumulating")
     A = d8.accum(dirs)
     torch.cuda.synchronize()
@@ -97,6 +96,13 @@ def test_counts_32768_identity():
     bad, A64 = identity_mismatches(dirs, A)
     assert bad == 0
     assert outlet_total(dirs, A64) == (dirs != 255).sum().item()
+    del A64
+    say("fused DEM -> counts equals flowdirs + accum")
+    A2, dirs2 = d8.accum_dem(z)
+    torch.cuda.synchronize()
+    assert d8.device_status() == d8.D8_OK
+    assert torch.equal(dirs2, dirs)
+    assert torch.equal(A2.view(torch.int32), A.view(torch.int32))
 
 
 def test_counts_serpentine_16384_closed_forms():

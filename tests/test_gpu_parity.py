@@ -121,6 +121,27 @@ def test_counts_deterministic_and_tile_invariant():
         np.testing.assert_array_equal(r, runs[0])
 
 
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("shape,nan", [((1, 1), 0), ((2, 300), 0), ((65, 63), 0.1), ((130, 257), 0), ((200, 129), 0.3),
+                                       ((300, 301), 0.02)])
+def test_accum_dem_fused(tile, shape, nan):
+    z = random_dem(*shape, 11, nan)
+    d = oracle.flowdirs(z)
+    counts, dirs = d8.accum_dem(to_dev(z), tile=tile)
+    assert d8.device_status() == d8.D8_OK
+    np.testing.assert_array_equal(to_np(dirs), d)
+    np.testing.assert_array_equal(to_np(counts), oracle.accum_u32(d))
+
+
+def test_accum_dem_fused_c0_nodata():
+    z = demgen.fbm_dem(700, 650, sigma=20.0, seed=5, nodata_frac=0.05, nodata_seed=6)
+    d = oracle.flowdirs(z)
+    for t in TILES:
+        counts, dirs = d8.accum_dem(to_dev(z), tile=t)
+        np.testing.assert_array_equal(to_np(dirs), d)
+        np.testing.assert_array_equal(to_np(counts), oracle.accum_u32(d))
+
+
 # ----------------------------------------------------------------- weighted
 
 @pytest.mark.parametrize("tile", [32, 64])
