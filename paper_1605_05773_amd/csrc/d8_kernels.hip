@@ -32,9 +32,10 @@ constexpr uint64_t kValMask = (1ull << 40) - 1;
 constexpr uint64_t kPendOne = 1ull << 40;
 
 // ------------------------------------------------------------------ flowdirs --
-// D8 "lowest of eight" (Sec. 1): a 16x16-thread block covers a 64x64-cell
-// tile; each thread owns a 4x4 patch and reads its 6x6 neighbourhood.
+// D8 "lowest of eight" (Sec. 1): a 16x8-thread block covers a 64x64-cell
+// block; each thread owns 4 columns x 8 rows and reads its 10x6 neighbourhood.
 constexpr int kFdTile = 64;
+constexpr int kFdRows = 8;  // rows per thread (measured best of 4, 8, 16)
 
 __device__ __forceinline__ uint8_t lowest8(float c, float n0, float n1, float n2, float n3, float n4, float n5,
                                            float n6, float n7) {
@@ -74,9 +75,11 @@ __device__ __forceinline__ uint8_t steepest8(float c, float n0, float n1, float 
   return k;
 }
 
-template <bool STEEP>
-__global__ __launch_bounds__(256) void k_flowdirs(const float* __restrict__ dem, uint8_t* __restrict__ dirs,
-                                                   DemTable tab) {
+// A 16 x (64 / RPT) thread block covers a 64 x 64 block of cells; each thread
+// owns 4 columns x RPT rows and reads its (RPT + 2) x 6 neighbourhood.
+template <bool STEEP, int RPT>
+__global__ __launch_bounds__(16 * (64 / RPT)) void k_flowdirs(const float* __restrict__ dem,
+                                                             uint8_t* __restrict__ dirs, DemTable tab) {
   const int64_t tile = blockIdx.x;
   const DemInfo dm = dem_of_tile(tab, tile);
   const int64_t lt = tile - dm.tile0;
@@ -84,22 +87,40 @@ __global__ __launch_bounds__(256) void k_flowdirs(const float* __restrict__ dem,
   const int64_t H = dm.H, W = dm.W;
   const float* z = dem + dm.off;
   uint8_t* d = dirs + dm.off;
-  const int64_t y0 = ty * kFdTile + 4 * threadIdx.y;
+  const int64_t y0 = ty * kFdTile + RPT * threadIdx.y;
   const int64_t x0 = tx * kFdTile + 4 * threadIdx.x;
   if (y0 >= H || x0 >= W) return;
-  float v[6][6];
+  float v[RPT + 2][6];
+  // Threads whose neighbourhood lies inside the DEM read the middle four
+  // columns of each row as one aligned 16-byte load.
+  const bool vec = ((reinterpret_cast<uintptr_t>(z) & 15) == 0) && (W & 3) == 0 && y0 >= 1 && y0 + RPT < H &&
+                   x0 >= 1 && x0 + 4 < W;
+  if (vec) {
 #pragma unroll
-  for (int rr = 0; rr < 6; ++rr) {
-    const int64_t yy = y0 - 1 + rr;
-    const bool rin = yy >= 0 && yy < H;
+    for (int rr = 0; rr < RPT + 2; ++rr) {
+      const float* row = z + (y0 - 1 + rr) * W + x0;
+      const float4 q = *reinterpret_cast<const float4*>(row);
+      v[rr][0] = row[-1];
+      v[rr][1] = q.x;
+      v[rr][2] = q.y;
+      v[rr][3] = q.z;
+      v[rr][4] = q.w;
+      v[rr][5] = row[4];
+    }
+  } else {
 #pragma unroll
-    for (int cc = 0; cc < 6; ++cc) {
-      const int64_t xx = x0 - 1 + cc;
-      v[rr][cc] = (rin && xx >= 0 && xx < W) ? z[yy * W + xx] : 0.0f;
+    for (int rr = 0; rr < RPT + 2; ++rr) {
+      const int64_t yy = y0 - 1 + rr;
+      const bool rin = yy >= 0 && yy < H;
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc) {
+        const int64_t xx = x0 - 1 + cc;
+        v[rr][cc] = (rin && xx >= 0 && xx < W) ? z[yy * W + xx] : 0.0f;
+      }
     }
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
+  for (int a = 0; a < RPT; ++a) {
     const int64_t y = y0 + a;
     if (y >= H) break;
     uint8_t code[4];
@@ -1467,10 +1488,11 @@ hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, 
 
 hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab, int64_t nblocks, hipStream_t s,
                            bool steepest) {
+  constexpr int RPT = kFdRows;
   if (steepest)
-    hipLaunchKernelGGL(k_flowdirs<true>, dim3((unsigned)nblocks), dim3(16, 16), 0, s, dem, dirs, tab);
+    hipLaunchKernelGGL((k_flowdirs<true, RPT>), dim3((unsigned)nblocks), dim3(16, 64 / RPT), 0, s, dem, dirs, tab);
   else
-    hipLaunchKernelGGL(k_flowdirs<false>, dim3((unsigned)nblocks), dim3(16, 16), 0, s, dem, dirs, tab);
+    hipLaunchKernelGGL((k_flowdirs<false, RPT>), dim3((unsigned)nblocks), dim3(16, 64 / RPT), 0, s, dem, dirs, tab);
   return hipGetLastError();
 }
 
