@@ -336,6 +336,15 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
   return x;
 }
 
+// Termination flags of the doubling loops: two LDS words used alternately,
+// so each round needs only its two barriers (a reduction barrier would add
+// two more).  Round j sets flag[j & 1] after the middle barrier; thread 0
+// clears flag[(j + 1) & 1], which every thread finished reading before that
+// barrier.
+struct RoundFlag {
+  uint32_t f[2];
+};
+
 // --------------------------------------------------- counts: tile doubling --
 // A workgroup owns a BW x BH block of cells made of whole TS x TS tiles (the
 // tiles of a block are independent).  Inside a tile the up-slope area with
@@ -512,6 +521,9 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
   // happen before the barrier, updates after it.  The saturating pointer
   // becomes the ancestor's saturating pointer when the exact one runs out.
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
+  __shared__ RoundFlag rf;
+  if (threadIdx.x == 0) rf.f[0] = rf.f[1] = 0;
+  __syncthreads();
   for (int round = 0;; ++round) {
     V v[CPT];
     uint32_t nl[CPT];
@@ -523,6 +535,7 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
     bool more = false;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -535,7 +548,9 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
         more |= na != kNoAnc;
       }
     }
-    if (!__syncthreads_or(more)) break;
+    if (more) rf.f[round & 1] = 1;
+    __syncthreads();
+    if (!rf.f[round & 1]) break;
     if (round >= max_rounds) {
       set_status(status, kStCycle);  // a cycle never runs out of ancestors
       break;
@@ -831,6 +846,9 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
   __syncthreads();
 
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
+  __shared__ RoundFlag rf;
+  if (threadIdx.x == 0) rf.f[0] = rf.f[1] = 0;
+  __syncthreads();
   for (int round = 0;; ++round) {
     double sa[CPT];
     uint32_t nl[CPT];
@@ -842,6 +860,7 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
     bool more = false;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -856,7 +875,9 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
         more |= na != kNoAnc;
       }
     }
-    if (!__syncthreads_or(more)) break;
+    if (more) rf.f[round & 1] = 1;
+    __syncthreads();
+    if (!rf.f[round & 1]) break;
     if (round >= max_rounds) {
       set_status(status, kStCycle);
       break;
@@ -1096,6 +1117,9 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   }
 
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)NN);
+  __shared__ RoundFlag rf;
+  if (threadIdx.x == 0) rf.f[0] = rf.f[1] = 0;
+  __syncthreads();
   for (int round = 0;; ++round) {
     LV v[NPT];
     uint32_t nl[NPT];
@@ -1107,6 +1131,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
     bool more = false;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
@@ -1119,7 +1144,9 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
         more |= na != kNoAnc;
       }
     }
-    if (!__syncthreads_or(more)) break;
+    if (more) rf.f[round & 1] = 1;
+    __syncthreads();
+    if (!rf.f[round & 1]) break;
     if (round >= max_rounds) {
       set_status(status, kStCycle);
       break;
