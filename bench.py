@@ -106,6 +106,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwdbwd", action="store_true")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (profiler calibration of byte counters)")
     args = ap.parse_args()
@@ -243,6 +244,45 @@ def main():
                             "ratio": round(f_ms / fb_ms, 4)}
         log(f"fwd/bwd: {extra['fwd_bwd']}")
         del d3, w3, g3, o3, ws3
+
+    if not args.no_batch:
+        # The batched differentiable form on the 512-DEM workload (sizes per
+        # the log-uniform recipe, lognormal weights and upstream gradients):
+        # forward alone vs forward + backward, each replayed as one HIP graph.
+        shapes, dems, ws4, gs4 = demgen.c4_batch()
+        b = d8.Batch(shapes, dev)
+        dp = d8.flowdirs_batched(b, b.pack([torch.from_numpy(x) for x in dems], torch.float32))
+        cells4 = b.total
+        gr = d8.BatchedGraph(b)
+        gr.dirs.copy_(dp)
+        gr.w.copy_(b.pack([torch.from_numpy(x) for x in ws4], torch.float32))
+        gr.g.copy_(b.pack([torch.from_numpy(x) for x in gs4], torch.float32))
+        gr.capture()
+        fwd_graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(fwd_graph):
+            d8.accum_batched(b, gr.dirs, gr.w, out=gr.area, ws=gr.ws)
+        for _ in range(2):
+            fwd_graph.replay()
+            gr.replay()
+        torch.cuda.synchronize()
+        if gr.status() != d8.D8_OK:
+            raise SystemExit("device status error in the batched workload")
+        c0, c1_, c2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        c0.record(stream)
+        for _ in range(args.steps):
+            fwd_graph.replay()
+        c1_.record(stream)
+        for _ in range(args.steps):
+            gr.replay()
+        c2.record(stream)
+        torch.cuda.synchronize()
+        bf = c0.elapsed_time(c1_) / args.steps
+        bfb = c1_.elapsed_time(c2) / args.steps
+        extra["batched_graph"] = {"workload": f"{len(shapes)} DEMs, {cells4} cells (sides log-uniform 64..2048)",
+                                  "fwd_gcells": round(cells4 / bf / 1e6, 2), "fwd_bwd_gcells": round(cells4 / bfb / 1e6, 2),
+                                  "fwd_ms": round(bf, 4), "fwd_bwd_ms": round(bfb, 4), "ratio": round(bf / bfb, 4)}
+        log(f"batched graph: {extra['batched_graph']}")
+        del gr, fwd_graph, dp
 
     if args.calib_copy:
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)

@@ -449,7 +449,7 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return D8_EHIP;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return D8_EHIP;
   }
   const int tiles[2] = {32, 64};
@@ -464,12 +464,12 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
       float ms_best = 1e30f;
       bool ok = true;
       for (int rep = 0; rep < 3 && ok; ++rep) {
-        hipEventRecord(e0, s);
+        (void)hipEventRecord(e0, s);
         d8_status a = d8_accum_batched(dirs_packed, host_desc, dev_desc, n, w_packed, D8_F32, out_scratch, nullptr,
                                        ws, ws_bytes, t, w, stream);
         d8_status b = d8_accum_backward_batched(dirs_packed, host_desc, dev_desc, n, out_scratch, g_scratch, ws,
                                                 ws_bytes, t, w, stream);
-        hipEventRecord(e1, s);
+        (void)hipEventRecord(e1, s);
         if (a != D8_OK || b != D8_OK) {
           ok = false;
           last = a != D8_OK ? a : b;
@@ -481,7 +481,7 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
           break;
         }
         float ms = 0;
-        hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0) ms_best = std::min(ms_best, ms);
       }
       if (ok && ms_best < best) {
@@ -491,8 +491,8 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (!bt) return last == D8_OK ? D8_EUNSUPPORTED : last;
   *best_tile = bt;
   *best_waves = bw;
