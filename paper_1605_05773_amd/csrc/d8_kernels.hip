@@ -23,7 +23,8 @@
 namespace d8 {
 
 // Optional per-phase cycle stamps for measurement builds (no-op here):
-// D8_STAMP(pass, i) marks the start of phase i of pass 0 (emit) or 1.
+// D8_STAMP(pass, i) marks the start of phase i of pass 0 (emit), 1 (finalise),
+// 2 (super-block up) or 3 (super-block down).
 #ifndef D8_STAMP
 #define D8_STAMP(pass, i)
 #endif
@@ -1015,6 +1016,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   __shared__ uint32_t link[NN];
   __shared__ uint8_t flag[NN];  // bit 0: an exit of its tile; bit 1: leaves the super-block
   const int tid = threadIdx.x;
+  D8_STAMP(DOWN ? 3 : 2, 0);
   const int64_t sbid = xcd_tile(blockIdx.x, nsb);
   const DemInfo dm = dem_of_sb(tab, sbid);
   const int64_t lsb = sbid - dm.sb0;
@@ -1027,6 +1029,53 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   uint16_t a[NPT];
   int32_t tg[NPT];   // super-block exits: the tile exit the target receiver leads to
   uint16_t tin[NPT];  // exits inside the super-block: the node of their target receiver
+  // Loads in three rounds (codes; then exit values and the target receivers'
+  // links), each issued for all of a thread's nodes before any is used.
+  int64_t sl[NPT];
+  uint8_t ec[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = tid + k * NT;
+    const int tl = n / CAP, j = n - tl * CAP;
+    const int ta = tl / G, tb = tl - ta * G;
+    const int64_t ty = ty0 + ta, tx = tx0 + tb;
+    sl[k] = (dm.tile0 + ty * dm.TX + tx) * CAP + j;
+    ec[k] = (n < NN && ty < dm.TY && tx < dm.TX) ? ex_code[sl[k]] : (uint8_t)0xFF;
+  }
+  int64_t tb_[NPT];   // target receiver's tile slot base
+  int rs_[NPT];       // target receiver's perimeter slot
+  int tn_[NPT];       // first node of the target tile when it is inside the super-block, else -1
+  LV v_[NPT];
+  uint16_t lk_[NPT];
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int n = tid + k * NT;
+    v_[k] = 0;
+    lk_[k] = 0xFFFF;
+    tb_[k] = 0;
+    rs_[k] = 0;
+    tn_[k] = -1;
+    if (ec[k] < 8) {
+      const int tl = n / CAP, j = n - tl * CAP;
+      const int ta = tl / G, tb = tl - ta * G;
+      const int64_t ty = ty0 + ta, tx = tx0 + tb;
+      const int th = (int)min((int64_t)TS, (int64_t)dm.H - ty * TS);
+      const int tw = (int)min((int64_t)TS, (int64_t)dm.W - tx * TS);
+      int r, c;
+      perim_cell(j, tw, th, r, c);
+      const int64_t gy = ty * TS + r + ddr_t(ec[k]), gx = tx * TS + c + ddc_t(ec[k]);
+      // the target receiver's tile and its slot there
+      const int64_t tty = gy / TS, ttx = gx / TS;
+      const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
+      const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
+      tb_[k] = (dm.tile0 + tty * dm.TX + ttx) * CAP;
+      rs_[k] = perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth);
+      if (gy >= y0 && gy < y0 + sbh && gx >= x0 && gx < x0 + sbw)
+        tn_[k] = (int)(((tty - ty0) * G + (ttx - tx0)) * CAP);
+      v_[k] = (LV)ex_val[sl[k]];
+      lk_[k] = rl[tb_[k] + rs_[k]];
+    }
+  }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     const int n = tid + k * NT;
@@ -1034,46 +1083,28 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
     tg[k] = -1;
     tin[k] = kNoAnc;
     if (n >= NN) continue;
-    const int tl = n / CAP, j = n - tl * CAP;
-    const int ta = tl / G, tb = tl - ta * G;
-    const int64_t ty = ty0 + ta, tx = tx0 + tb;
-    const bool tile_ok = ty < dm.TY && tx < dm.TX;
-    const int64_t s = (dm.tile0 + ty * dm.TX + tx) * CAP + j;
-    const uint8_t ec = tile_ok ? ex_code[s] : (uint8_t)0xFF;
-    LV v = 0;
     uint8_t f = 0;
-    if (ec < 8) {
+    if (ec[k] < 8) {
       f = 1;
-      v = (LV)ex_val[s];
-      const int th = (int)min((int64_t)TS, (int64_t)dm.H - ty * TS);
-      const int tw = (int)min((int64_t)TS, (int64_t)dm.W - tx * TS);
-      int r, c;
-      perim_cell(j, tw, th, r, c);
-      const int64_t gy = ty * TS + r + ddr_t(ec), gx = tx * TS + c + ddc_t(ec);
-      // the target receiver's tile and its slot there
-      const int64_t tty = gy / TS, ttx = gx / TS;
-      const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
-      const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
-      const int64_t tbase = (dm.tile0 + tty * dm.TX + ttx) * CAP;
-      const int rs = perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth);
-      const uint16_t lk = rl[tbase + rs];
-      if (gy >= y0 && gy < y0 + sbh && gx >= x0 && gx < x0 + sbw) {
-        const int tnode = (int)(((tty - ty0) * G + (ttx - tx0)) * CAP);
+      const uint16_t lk = lk_[k];
+      if (tn_[k] >= 0) {
+        const int tnode = tn_[k];
         if (lk != 0xFFFF) a[k] = (uint16_t)(tnode + lk);
-        tin[k] = (uint16_t)(tnode + rs);
+        tin[k] = (uint16_t)(tnode + rs_[k]);
       } else {
         f |= 2;
         // super-block exit: remember the tile exit its target receiver leads
         // to; the global resolve turns it into a parent via that exit's
         // super-block root
-        tg[k] = lk == 0xFFFF ? -1 : (int32_t)(tbase + lk);
+        tg[k] = lk == 0xFFFF ? -1 : (int32_t)(tb_[k] + lk);
       }
     }
-    val[n] = v;
+    val[n] = v_[k];
     link[n] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)n) << 16);
     flag[n] = f;
   }
   __syncthreads();
+  D8_STAMP(DOWN ? 3 : 2, 1);
   constexpr int NPB = (4 * kSuper - 4 + NT - 1) / NT;  // super-block perimeter cells per thread
   V xb[NPB];
   int nb[NPB];
@@ -1081,6 +1112,41 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
     // Resolved inflow of every receiver on the super-block's border, added at
     // the tile exit its in-tile path leaves by.
     const int P = perim_count(sbw, sbh);
+    // Three load rounds, each issued for every cell and direction before any
+    // is used: the outside neighbours' exit codes; the super-block roots of
+    // those that drain into the border cell; the roots' resolved inflows.
+    uint8_t en[NPB][8];
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      const int i = tid + q * NT;
+      int r = 0, c = 0;
+      if (i < P) perim_cell(i, sbw, sbh, r, c);
+      const int64_t gy = y0 + r, gx = x0 + c;
+      const uint32_t out = i < P ? outside_dirs(r, c, sbw, sbh) : 0u;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        en[q][d] = 0xFF;
+        const int64_t ny = gy + ddr_t(d), nx = gx + ddc_t(d);
+        if ((out & (1u << d)) && ny >= 0 && ny < dm.H && nx >= 0 && nx < dm.W) {
+          const uint8_t e = ex_code[slot_of_cell(dm, ny, nx, TS, CAP)];
+          // only neighbours whose exit step lands on this border cell count
+          en[q][d] = (e < 8 && ddr_t(e) == -ddr_t(d) && ddc_t(e) == -ddc_t(d)) ? e : (uint8_t)0xFF;
+        }
+      }
+    }
+    int32_t rt[NPB][8];
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      const int i = tid + q * NT;
+      int r = 0, c = 0;
+      if (i < P) perim_cell(i, sbw, sbh, r, c);
+      const int64_t gy = y0 + r, gx = x0 + c;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        rt[q][d] = -1;
+        if (en[q][d] != 0xFF) rt[q][d] = sbroot[slot_of_cell(dm, gy + ddr_t(d), gx + ddc_t(d), TS, CAP)];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NPB; ++q) {
       const int i = tid + q * NT;
@@ -1090,16 +1156,10 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
       int r, c;
       perim_cell(i, sbw, sbh, r, c);
       const int64_t gy = y0 + r, gx = x0 + c;
-      const uint32_t out = outside_dirs(r, c, sbw, sbh);
       V x = 0;
-      for (int d = 0; d < 8; ++d) {
-        if (!(out & (1u << d))) continue;
-        const int64_t ny = gy + ddr_t(d), nx = gx + ddc_t(d);
-        if (ny < 0 || ny >= dm.H || nx < 0 || nx >= dm.W) continue;
-        const int64_t ns = slot_of_cell(dm, ny, nx, TS, CAP);
-        const uint8_t ecn = ex_code[ns];
-        if (ecn < 8 && ny + ddr_t(ecn) == gy && nx + ddc_t(ecn) == gx) x += F[sbroot[ns]];
-      }
+#pragma unroll
+      for (int d = 0; d < 8; ++d)
+        if (en[q][d] != 0xFF) x += F[rt[q][d]];
       if (x != (V)0) {
         const int64_t tty = gy / TS, ttx = gx / TS;
         const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
@@ -1117,6 +1177,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   }
 
   const int max_rounds = 2 + 31 - __builtin_clz((unsigned)NN);
+  D8_STAMP(DOWN ? 3 : 2, 2);
   __shared__ RoundFlag rf;
   if (threadIdx.x == 0) rf.f[0] = rf.f[1] = 0;
   __syncthreads();
@@ -1154,6 +1215,7 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   }
   __syncthreads();
 
+  D8_STAMP(DOWN ? 3 : 2, 3);
   if (DOWN) {
     // Full areas of the tile exits, then the inflow of every receiver slot of
     // the super-block's tiles (Alg. 7's incoming area): the exits inside the
@@ -1192,6 +1254,8 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
       if (ty0 + ta < dm.TY && tx0 + tb < dm.TX)
         xin[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (V)val[n];
     }
+    D8_STAMP(DOWN ? 3 : 2, 4);
+    D8_STAMP(DOWN ? 3 : 2, 5);
     return;
   }
   // Dense node ids for the super-block exits: one global atomic per
@@ -1237,6 +1301,8 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
       sbroot[(dm.tile0 + (ty0 + ta) * dm.TX + tx0 + tb) * CAP + j] = (flag[r] & 2) ? (int32_t)link[r] : -1;
     }
   }
+  D8_STAMP(DOWN ? 3 : 2, 4);
+  D8_STAMP(DOWN ? 3 : 2, 5);
 }
 
 // Global resolve over super-block exits.  Node = a super-block exit (dense
