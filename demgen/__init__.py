@@ -141,8 +141,10 @@ def _say(msg):
 
 
 def fbm_dem(rows: int, cols: int, sigma: float, seed: int, hurst: float = 0.7, slope: float = 0.01,
-            eps: float = 1e-3, nodata_frac: float = 0.0, nodata_seed: int = 0) -> np.ndarray:
-    """The full DEM recipe: fBm + tilt -> float32 -> NoData disks -> eps fill."""
+            eps: float = 1e-3, nodata_frac: float = 0.0, nodata_seed: int = 0, fill: bool = True) -> np.ndarray:
+    """The full DEM recipe: fBm + tilt -> float32 -> NoData disks -> eps fill
+    (fill=False stops before the fill: the raw surface, with its pits and
+    closed depressions, that conditioning starts from)."""
     big = rows * cols >= (1 << 26)
     z64 = fbm(rows, cols, hurst, sigma, seed)
     if big:
@@ -151,7 +153,8 @@ def fbm_dem(rows: int, cols: int, sigma: float, seed: int, hurst: float = 0.7, s
     del z64
     if nodata_frac > 0:
         nodata_disks(z, nodata_frac, nodata_seed)
-    fill_eps(z, eps)
+    if fill:
+        fill_eps(z, eps)
     return z
 
 
@@ -283,9 +286,14 @@ def cached(name: str, params: dict, make):
     return arr, m
 
 
-def config_dem(name: str, use_cache: bool = True) -> np.ndarray:
-    """DEM for a named workload (c0, c1, c2a, c3, c2b = serpentine 16384^2)."""
-    if name == "c2b":
+def config_dem(name: str, use_cache: bool = True, raw: bool = False) -> np.ndarray:
+    """DEM for a named workload (c0, c1, c2a, c3, c2b = serpentine 16384^2).
+    raw=True: the same surface before the epsilon fill (fBm workloads only)."""
+    if raw:
+        rows, cols, kw = CONFIGS[name]
+        params = dict(rows=rows, cols=cols, raw=True, **kw)
+        mk = lambda: fbm_dem(rows, cols, fill=False, **kw)
+    elif name == "c2b":
         params = {"rows": 16384, "cols": 16384}
         mk = lambda: serpentine_fast(16384, 16384)
     else:

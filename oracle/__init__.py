@@ -59,6 +59,8 @@ def lib():
         L.orc_backward_f64.argtypes = [P, I, I, P, P]
         L.orc_backward_f64d.argtypes = [P, I, I, P, P]
         L.orc_bruteforce_f64.argtypes = [P, I, I, P, P]
+        L.orc_fill_eps.restype = ctypes.c_int
+        L.orc_fill_eps.argtypes = [P, I, I, ctypes.c_float, P]
         L.orc_depth.restype = ctypes.c_int64
         L.orc_depth.argtypes = [P, I, I]
         _lib = L
@@ -86,6 +88,17 @@ def flowdirs(z: np.ndarray, rule: str = "lowest") -> np.ndarray:
     out = np.empty(z.shape, dtype=np.uint8)
     fn = {"lowest": lib().orc_flowdirs, "steepest": lib().orc_flowdirs_steepest}[rule]
     _check(fn(z.ctypes.data, z.shape[0], z.shape[1], out.ctypes.data))
+    return out
+
+
+def fill_eps(z: np.ndarray, eps: float = 1e-3) -> np.ndarray:
+    """Epsilon-filled DEM (float32): the unique F with F = z on seeds (valid
+    cells on the DEM boundary or next to NaN) and F(c) = max(z(c), min over
+    valid neighbours of inc(F(n))) elsewhere, inc(x) = fl32(x + eps) or the
+    next float above x.  Dijkstra order in d8_oracle.c.  NaN stays NaN."""
+    z = _c(z, np.float32)
+    out = np.empty(z.shape, dtype=np.float32)
+    _check(lib().orc_fill_eps(z.ctypes.data, z.shape[0], z.shape[1], ctypes.c_float(eps), out.ctypes.data))
     return out
 
 

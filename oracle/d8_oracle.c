@@ -327,3 +327,116 @@ out:
   free(indeg); free(tgt); free(order); free(d);
   return best;
 }
+
+/* ---------------------------------------------------------------------------
+ * Depression and flat conditioning (Sec. 3, the preprocessing the method
+ * assumes: pits raised to the level they drain at, flats given small
+ * elevation changes).  The paper names no algorithm; the reading taken here is
+ * the epsilon fill of Planchon & Darboux (2002):
+ *
+ *   seeds S = valid cells on the DEM boundary or 8-adjacent to NoData;
+ *   inc(x) = fl32(x + eps) if that is > x, else the next float above x;
+ *   F(s) = z(s) on S, and for every other valid cell
+ *   F(c) = max(z(c), min over valid neighbours n of inc(F(n))).
+ *
+ * That fixed point is unique (inc is strictly increasing), F >= z, and every
+ * non-seed cell has a neighbour lower than itself, so lowest-of-eight leaves
+ * outlets only at seeds.  Equivalently F(c) is the minimum over 8-connected
+ * paths c = p0, p1, ..., pk in S of max_i inc^i(z(p_i)).
+ *
+ * Computed here by Dijkstra's label-setting order on that path cost (a binary
+ * heap keyed by the monotone bits of F, ties by cell index, stale entries
+ * skipped): the cost through a settled cell u of a neighbour n is
+ * max(z(n), inc(F(u))), which is non-decreasing in F(u) and never below it.
+ * NaN cells stay NaN.  eps must be a positive normal float.
+ * ------------------------------------------------------------------------- */
+static uint32_t orc_fbits_key(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+static float orc_inc(float x, float eps) {
+  float y = x + eps;
+  if (!(y > x)) y = nextafterf(x, INFINITY);
+  return y;
+}
+
+typedef struct { uint64_t* a; size_t n, cap; } orc_heap;
+
+static int orc_heap_push(orc_heap* h, uint64_t k) {
+  if (h->n == h->cap) {
+    size_t nc = h->cap ? 2 * h->cap : 1024;
+    uint64_t* na = (uint64_t*)realloc(h->a, nc * sizeof(uint64_t));
+    if (!na) return -1;
+    h->a = na;
+    h->cap = nc;
+  }
+  size_t i = h->n++;
+  while (i > 0) {
+    size_t p = (i - 1) / 2;
+    if (h->a[p] <= k) break;
+    h->a[i] = h->a[p];
+    i = p;
+  }
+  h->a[i] = k;
+  return 0;
+}
+
+static uint64_t orc_heap_pop(orc_heap* h) {
+  uint64_t top = h->a[0], last = h->a[--h->n];
+  size_t i = 0;
+  for (;;) {
+    size_t l = 2 * i + 1;
+    if (l >= h->n) break;
+    size_t m = (l + 1 < h->n && h->a[l + 1] < h->a[l]) ? l + 1 : l;
+    if (h->a[m] >= last) break;
+    h->a[i] = h->a[m];
+    i = m;
+  }
+  if (h->n) h->a[i] = last;
+  return top;
+}
+
+int orc_fill_eps(const float* z, int64_t H, int64_t W, float eps, float* F) {
+  const int64_t N = H * W;
+  if (N > 0xFFFFFFFFll) return ORC_NOMEM;
+  uint8_t* done = (uint8_t*)calloc((size_t)(N ? N : 1), 1);
+  orc_heap h = {0, 0, 0};
+  int st = ORC_OK;
+  if (!done) return ORC_NOMEM;
+  for (int64_t r = 0; r < H; ++r) {
+    for (int64_t c = 0; c < W; ++c) {
+      const int64_t i = r * W + c;
+      if (isnan(z[i])) { F[i] = z[i]; continue; }
+      int seed = (r == 0 || c == 0 || r == H - 1 || c == W - 1);
+      for (int d = 0; d < 8 && !seed; ++d)
+        if (isnan(z[(r + ODR[d]) * W + c + ODC[d]])) seed = 1;
+      F[i] = seed ? z[i] : INFINITY;
+      if (seed && orc_heap_push(&h, ((uint64_t)orc_fbits_key(z[i]) << 32) | (uint64_t)i)) { st = ORC_NOMEM; goto out; }
+    }
+  }
+  while (h.n) {
+    const uint64_t k = orc_heap_pop(&h);
+    const int64_t u = (int64_t)(k & 0xFFFFFFFFu);
+    if (done[u] || (uint32_t)(k >> 32) != orc_fbits_key(F[u])) continue; /* stale */
+    done[u] = 1;
+    const int64_t r = u / W, c = u % W;
+    const float through = orc_inc(F[u], eps);
+    for (int d = 0; d < 8; ++d) {
+      const int64_t rr = r + ODR[d], cc = c + ODC[d];
+      if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+      const int64_t n = rr * W + cc;
+      if (done[n] || isnan(z[n])) continue;
+      const float cand = z[n] > through ? z[n] : through;
+      if (cand < F[n]) {
+        F[n] = cand;
+        if (orc_heap_push(&h, ((uint64_t)orc_fbits_key(cand) << 32) | (uint64_t)n)) { st = ORC_NOMEM; goto out; }
+      }
+    }
+  }
+out:
+  free(done);
+  free(h.a);
+  return st;
+}
