@@ -348,7 +348,10 @@ out:
  * heap keyed by the monotone bits of F, ties by cell index, stale entries
  * skipped): the cost through a settled cell u of a neighbour n is
  * max(z(n), inc(F(u))), which is non-decreasing in F(u) and never below it.
- * NaN cells stay NaN.  eps must be a positive normal float.
+ * NaN cells stay NaN.  eps must be a positive normal float.  Minimum and
+ * maximum are taken in the total order of the float bit patterns (the
+ * order of the values, with -0 below +0), so signed zeros are resolved the
+ * same way by any evaluation order.
  * ------------------------------------------------------------------------- */
 static uint32_t orc_fbits_key(float f) {
   uint32_t u;
@@ -428,8 +431,9 @@ int orc_fill_eps(const float* z, int64_t H, int64_t W, float eps, float* F) {
       if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
       const int64_t n = rr * W + cc;
       if (done[n] || isnan(z[n])) continue;
-      const float cand = z[n] > through ? z[n] : through;
-      if (cand < F[n]) {
+      /* max and < in the total order of the monotone bits (-0 below +0) */
+      const float cand = orc_fbits_key(z[n]) > orc_fbits_key(through) ? z[n] : through;
+      if (orc_fbits_key(cand) < orc_fbits_key(F[n])) {
         F[n] = cand;
         if (orc_heap_push(&h, ((uint64_t)orc_fbits_key(cand) << 32) | (uint64_t)n)) { st = ORC_NOMEM; goto out; }
       }

@@ -226,3 +226,15 @@ def test_raw_fbm_properties(eps):
     assert np.array_equal(d == 8, s)
     assert_same(F, np_jacobi_fill(z, np.float32(eps)))
     assert (F[v] > z[v]).any()
+
+
+def test_signed_zero_is_below_positive_zero():
+    """Ties between -0 and +0 follow the total order of the bit patterns: a
+    cell at -0 next to a seed at -eps is raised to inc(-eps) = +0."""
+    e = np.float32(1e-3)
+    z = np.full((3, 4), np.float32(5.0))
+    z[1, 0] = -e
+    z[1, 1] = np.float32(-0.0)
+    got = oracle.fill_eps(z, 1e-3)
+    assert got[1, 1].view(np.uint32) == np.float32(0.0).view(np.uint32)
+    assert got[1, 0] == -e
