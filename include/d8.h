@@ -27,7 +27,8 @@
  *   workspace of at least d8_*_workspace_bytes() bytes, 256-byte aligned.
  *   Outputs must not alias inputs.  Every call only enqueues work on `stream`
  *   (a hipStream_t; NULL = the default stream) and returns; there is no hidden
- *   synchronisation, so calls may be captured into a HIP graph.
+ *   synchronisation, so calls may be captured into a HIP graph (the one
+ *   exception, d8_fill_eps, says so).
  *
  * Errors
  *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, unsupported
@@ -134,6 +135,31 @@ d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* di
 
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Conditioning (Sec. 3 assumes the DEM is free of pits and flats before the
+ * method runs: a pit is raised to the level it drains at, flats get small
+ * elevation changes; the paper leaves the algorithm open).  Epsilon fill
+ * (Planchon & Darboux 2002): seeds are the valid cells on the DEM boundary or
+ * 8-adjacent to NaN and keep their elevation; every other valid cell gets the
+ * unique fixed point F(c) = max(z(c), min over valid neighbours n of
+ * inc(F(n))), inc(x) = fl32(x + eps) or, where that rounds back to x, the next
+ * float above x.  Min and max follow the total order of the float bits (-0
+ * below +0), so the result is exact and independent of evaluation order.
+ * Afterwards lowest-of-eight (d8_flowdirs) gives outlets exactly at the seeds.
+ *
+ * dem: float32 [rows*cols] (NaN = NoData); out: float32 [rows*cols] (output,
+ * NaN where dem is NaN; must not overlap dem).  eps: a positive normal float.
+ * ws: workspace of d8_fill_workspace_bytes(rows, cols) bytes, 256-aligned.
+ * rounds: NULL, or receives the number of tile rounds that had work.
+ * Unlike every other entry point this call SYNCHRONISES `stream`: it runs
+ * rounds of 64x64-tile relaxation until no tile changes, and reads the length
+ * of the next round's tile queue back to the host every few rounds.  Returns
+ * D8_ECYCLE if 2^24 rounds pass without convergence (not reachable for
+ * finite inputs in practice). */
+size_t d8_fill_workspace_bytes(int64_t rows, int64_t cols);
+d8_status d8_fill_eps(const float* dem, int64_t rows, int64_t cols, float eps, float* out, void* ws,
+                      size_t ws_bytes, int64_t* rounds, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Batched: n DEMs of uneven shapes packed in one buffer, one set of launches

@@ -56,6 +56,8 @@ def lib():
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
             "d8_accum_dem": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
+            "d8_fill_workspace_bytes": ([I64, I64], SZ),
+            "d8_fill_eps": ([P, I64, I64, ctypes.c_float, P, P, SZ, P, P], I32),
             "d8_batched_workspace_bytes": ([P, I32, I32], SZ),
             "d8_flowdirs_batched": ([P, P, P, I32, P, P, SZ, P], I32),
             "d8_accum_batched": ([P, P, P, I32, P, I32, P, P, P, SZ, I32, I32, P], I32),
@@ -79,6 +81,7 @@ EXPORTED = (
     "d8_flowdirs", "d8_flowdirs_steepest", "d8_workspace_bytes", "d8_accum", "d8_accum_dem", "d8_accum_backward",
     "d8_batched_workspace_bytes", "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
+    "d8_fill_workspace_bytes", "d8_fill_eps",
 )
 NPHASES = 10
 
@@ -183,6 +186,28 @@ def accum_dem(dem: torch.Tensor, *, tile: int = 0, out: torch.Tensor | None = No
     _check(lib().d8_accum_dem(dem.data_ptr(), H, W, dirs.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), tile,
                               _stream(dem.device)), "d8_accum_dem")
     return out, dirs
+
+
+def fill(dem: torch.Tensor, eps: float = 1e-3, *, out: torch.Tensor | None = None,
+         ws: torch.Tensor | None = None, return_rounds: bool = False):
+    """Epsilon-filled copy of a float32 DEM (NaN = NoData): pits and flats
+    raised so that lowest-of-eight drains every cell to the DEM boundary or
+    to NoData.  Synchronises the current stream.  With return_rounds, returns
+    (filled, number of tile rounds that had work)."""
+    dem = _dev_tensor(dem, torch.float32, "dem")
+    if dem.dim() != 2:
+        raise ValueError("dem must be 2-D")
+    H, W = dem.shape
+    out = torch.empty((H, W), dtype=torch.float32, device=dem.device) if out is None else out
+    _dev_tensor(out, torch.float32, "out")
+    nb = lib().d8_fill_workspace_bytes(H, W)
+    if nb == 0:
+        raise D8Error(D8_EINVAL, "d8_fill_workspace_bytes")
+    ws = workspace(nb, dem.device) if ws is None else ws
+    rounds = ctypes.c_int64(0)
+    _check(lib().d8_fill_eps(dem.data_ptr(), H, W, ctypes.c_float(eps), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                             ctypes.byref(rounds), _stream(dem.device)), "d8_fill_eps")
+    return (out, rounds.value) if return_rounds else out
 
 
 def accum_backward(dirs: torch.Tensor, grad_out: torch.Tensor, *, tile: int = 0,

@@ -335,6 +335,66 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
   return run_backward(p, dirs, grad_out, grad_weights, 0, (hipStream_t)stream);
 }
 
+// ------------------------------------------------------------- conditioning --
+
+static int64_t fill_tiles(int64_t rows, int64_t cols) {
+  return ((rows + kFillTile - 1) / kFillTile) * ((cols + kFillTile - 1) / kFillTile);
+}
+size_t d8_fill_workspace_bytes(int64_t rows, int64_t cols) {
+  if (!shape_ok(rows, cols)) return 0;
+  return 256 + 3 * align256((size_t)fill_tiles(rows, cols) * sizeof(uint32_t));
+}
+
+d8_status d8_fill_eps(const float* dem, int64_t rows, int64_t cols, float eps, float* out, void* ws,
+                      size_t ws_bytes, int64_t* rounds, void* stream) {
+  if (!dem || !out || !ws || !shape_ok(rows, cols)) return D8_EINVAL;
+  if (!(eps >= 1.17549435e-38f) || !std::isfinite(eps)) return D8_EINVAL;  // positive normal
+  const size_t nb = (size_t)rows * (size_t)cols * sizeof(float);
+  const char* zb = reinterpret_cast<const char*>(dem);
+  const char* ob = reinterpret_cast<const char*>(out);
+  if (ob < zb + nb && zb < ob + nb) return D8_EINVAL;  // out overlaps dem
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
+  if (ws_bytes < d8_fill_workspace_bytes(rows, cols)) return D8_ENOMEM;
+  const int64_t nt = fill_tiles(rows, cols);
+  const size_t qb = align256((size_t)nt * sizeof(uint32_t));
+  char* base = static_cast<char*>(ws);
+  FillArgs a;
+  a.z = dem;
+  a.F = out;
+  a.H = rows;
+  a.W = cols;
+  a.TY = (rows + kFillTile - 1) / kFillTile;
+  a.TX = (cols + kFillTile - 1) / kFillTile;
+  a.eps = eps;
+  a.cnt = reinterpret_cast<uint32_t*>(base);
+  a.qround = reinterpret_cast<uint32_t*>(base + 256);
+  a.queue[0] = reinterpret_cast<uint32_t*>(base + 256 + qb);
+  a.queue[1] = reinterpret_cast<uint32_t*>(base + 256 + 2 * qb);
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_fill_reset(a, s) != hipSuccess) return D8_EHIP;
+  // Round r drains queue r and fills queue r+1; the host looks at the length
+  // of the next queue now and then (round 0 queues every tile once more).
+  const uint32_t kMaxFillRounds = 1u << 24;
+  for (uint32_t r = 0;; ++r) {
+    if (launch_fill_round(a, r, s) != hipSuccess) return D8_EHIP;
+    if (r == 0 || !(r <= 4 || r % 16 == 0)) continue;
+    uint32_t next = 0;
+    if (hipMemcpyAsync(&next, a.cnt + (r + 1) % 3, sizeof(next), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return D8_EHIP;
+    if (next == 0) break;
+    if (r >= kMaxFillRounds) return D8_ECYCLE;
+  }
+  if (rounds) {
+    uint32_t used = 0;
+    if (hipMemcpyAsync(&used, a.cnt + 3, sizeof(used), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return D8_EHIP;
+    *rounds = used;
+  }
+  return D8_OK;
+}
+
 // ------------------------------------------------------------------ batched --
 
 static bool batch_tiles(const d8_desc* hd, int32_t n, int ts, int64_t& ntiles) {

@@ -74,4 +74,20 @@ hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float
 hipError_t launch_forward_resolve(const Plan& p, bool weighted, hipStream_t s);
 hipError_t launch_backward_resolve(const Plan& p, hipStream_t s);
 
+// Epsilon fill over 64x64 tiles.  Workspace: cnt (4 words: the queue lengths
+// of three rotating rounds, then the number of rounds that had work), qround
+// (per tile: the last round it was queued for) and two tile queues.
+constexpr int kFillTile = 64;
+struct FillArgs {
+  const float* z = nullptr;
+  float* F = nullptr;
+  int64_t H = 0, W = 0, TX = 0, TY = 0;
+  float eps = 0.0f;
+  uint32_t* cnt = nullptr;
+  uint32_t* qround = nullptr;
+  uint32_t* queue[2] = {nullptr, nullptr};
+};
+hipError_t launch_fill_reset(const FillArgs& a, hipStream_t s);
+hipError_t launch_fill_round(const FillArgs& a, uint32_t round, hipStream_t s);
+
 }  // namespace d8

@@ -79,3 +79,27 @@ def test_batched_workspace_validation():
     bad = (d8.d8_desc * 1)(d8.d8_desc(0, 0, 20))
     assert L.d8_batched_workspace_bytes(ctypes.addressof(bad), 1, 64) == 0
     assert L.d8_batched_workspace_bytes(ctypes.addressof(descs), 0, 64) == 0
+
+
+def test_fill_argument_errors_before_device_work():
+    L = d8.lib()
+    fake = ctypes.c_void_p(0x10000)
+    out = ctypes.c_void_p(0x900000)
+    ws = ctypes.c_void_p(0x1000000)
+    assert L.d8_fill_workspace_bytes(0, 5) == 0
+    assert L.d8_fill_workspace_bytes(1 << 17, 1 << 16) == 0
+    nb = L.d8_fill_workspace_bytes(100, 100)
+    assert nb >= 256 + 3 * 4 * 4 and nb % 256 == 0
+    assert L.d8_fill_workspace_bytes(1000, 1000) > nb
+    f = L.d8_fill_eps
+    c = ctypes.c_float
+    assert f(None, 100, 100, c(1e-3), out, ws, nb, None, None) == d8.D8_EINVAL
+    assert f(fake, 100, 100, c(1e-3), None, ws, nb, None, None) == d8.D8_EINVAL
+    assert f(fake, 0, 100, c(1e-3), out, ws, nb, None, None) == d8.D8_EINVAL
+    for bad in (0.0, -1e-3, float("nan"), float("inf"), 1e-40):     # eps must be a positive normal float
+        assert f(fake, 100, 100, c(bad), out, ws, nb, None, None) == d8.D8_EINVAL, bad
+    # out overlapping dem (same buffer, and a partial overlap)
+    assert f(fake, 100, 100, c(1e-3), fake, ws, nb, None, None) == d8.D8_EINVAL
+    assert f(fake, 100, 100, c(1e-3), ctypes.c_void_p(0x10000 + 400), ws, nb, None, None) == d8.D8_EINVAL
+    assert f(fake, 100, 100, c(1e-3), out, ctypes.c_void_p(0x1000010), nb, None, None) == d8.D8_EINVAL
+    assert f(fake, 100, 100, c(1e-3), out, ws, nb - 1, None, None) == d8.D8_ENOMEM

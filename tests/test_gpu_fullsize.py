@@ -227,3 +227,30 @@ def test_c4_batch_vs_oracle():
         np.testing.assert_array_equal(to_np(C[i]), oracle.accum_u32(dirs[i]), err_msg=f"dem {i}")
         assert_rel(to_np(A[i]), oracle.accum_f64(dirs[i], ws[i]), 1e-6, f"batched weighted {i}")
         assert_rel(to_np(G[i]), oracle.backward_f64(dirs[i], gs[i]), 1e-6, f"batched backward {i}")
+
+
+# --------------------------------------------- conditioning at 8192^2 (oracle)
+
+def test_c1_raw_fill_exact():
+    """The 8192^2 surface with NoData disks before conditioning: the GPU fill
+    equals the oracle bit for bit, and lowest-of-eight on it leaves outlets
+    only on the DEM boundary and next to NoData."""
+    say("raw c1 surface")
+    z = demgen.config_dem("c1", raw=True)
+    say("GPU fill")
+    Fg, rounds = d8.fill(to_dev(z), 1e-3, return_rounds=True)
+    say(f"rounds {rounds}; oracle fill")
+    F = oracle.fill_eps(z, 1e-3)
+    got = to_np(Fg)
+    assert np.array_equal(got.view(np.uint32), F.view(np.uint32))
+    dg = to_np(d8.flowdirs(Fg))
+    seeds = ~np.isnan(z)
+    inner = np.zeros_like(seeds)
+    inner[1:-1, 1:-1] = True
+    nan = np.isnan(z)
+    near = nan.copy()
+    for dr in (-1, 0, 1):
+        for dc in (-1, 0, 1):
+            near |= np.roll(np.roll(nan, dr, 0), dc, 1)
+    seeds &= ~inner | near
+    assert np.array_equal(dg == 8, seeds)
