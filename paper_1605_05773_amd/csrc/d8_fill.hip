@@ -30,6 +30,12 @@
 
 #include "d8_internal.hpp"
 
+// Optional per-visit statistics for measurement builds (no-op here):
+// D8_FILL_STAT(round, sweep sets, start clock) at the end of a tile visit.
+#ifndef D8_FILL_STAT
+#define D8_FILL_STAT(round, sets, t0)
+#endif
+
 namespace d8 {
 namespace {
 
@@ -37,7 +43,8 @@ constexpr int kFT = 64;            // tile side
 constexpr int kFK = kFT + 3;       // row stride of the key array (halo ring + 1 pad: odd)
 constexpr int kFZ = kFT + 1;       // row stride of the elevation array (odd)
 constexpr int kFThreads = 256;     // four waves
-constexpr uint32_t kKeyInf = 0xFF800000u;  // key of +inf: also "no value" (outside, NaN)
+constexpr uint32_t kKeyInf = 0xFF800000u;   // key of +inf (a valid cell not reached yet)
+constexpr uint32_t kKeyNone = 0xFFFFFFFFu;  // no cell: outside the DEM or NaN (above every key)
 constexpr int kFillSweepCap = 255;         // sweep sets per tile visit
 
 __device__ __forceinline__ uint32_t fkey(float f) {
@@ -56,6 +63,42 @@ __device__ __forceinline__ float inc_eps(float x, float eps) {
   return __uint_as_float(x > 0.0f ? u + 1u : u - 1u);  // next float above x (x != 0 here)
 }
 
+// Thread layout of the global loads and stores: wave w (of four) takes rows
+// w, w + 4, ..., its lane the column, so each wave touches one contiguous row
+// segment per step and the per-step address offset is uniform.
+constexpr int kHR = (kFT + 2 + 3) / 4;  // steps over the kFT+2 rows of the halo tile
+constexpr int kTR = kFT / 4;            // steps over the kFT rows of the tile
+
+// The halo tile of src, rows y0-1 .. y0+kFT, columns x0-1 .. x0+kFT (NaN
+// outside the DEM): v[p] is column lane-1 of halo row 4p+w, e[p] (lanes 0
+// and 1) column kFT-1+lane.  Every load is issued before any is used.
+__device__ __forceinline__ void load_halo_tile(const float* __restrict__ src, int64_t y0, int64_t x0, int64_t H,
+                                               int64_t W, float (&v)[kHR], float (&e)[kHR]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t gx = x0 - 1 + lane, gx2 = x0 + kFT - 1 + lane;
+  const bool cx = gx >= 0 && gx < W, cx2 = lane < 2 && gx2 < W;
+  const float* p0 = src + (y0 - 1 + w) * W;
+#pragma unroll
+  for (int p = 0; p < kHR; ++p) {
+    const int64_t gy = y0 - 1 + 4 * p + w;
+    const bool cy = 4 * p + w < kFT + 2 && gy >= 0 && gy < H;
+    const float* row = p0 + (int64_t)(4 * p) * W;
+    v[p] = cy && cx ? row[gx] : __builtin_nanf("");
+    e[p] = cy && cx2 ? row[gx2] : __builtin_nanf("");
+  }
+}
+
+// Position in the key array of the i-th cell of the halo ring (top row, bottom
+// row, left column, right column).
+__device__ __forceinline__ int ring_index(int j) {
+  int r, c;
+  if (j < kFT + 2) { r = 0; c = j; }
+  else if (j < 2 * (kFT + 2)) { r = kFT + 1; c = j - (kFT + 2); }
+  else if (j < 3 * (kFT + 2) - 2) { r = j - 2 * (kFT + 2) + 1; c = 0; }
+  else { r = j - 3 * (kFT + 2) + 3; c = kFT + 1; }
+  return r * kFK + c;
+}
+
 __device__ __forceinline__ void fill_enqueue(const FillArgs& a, uint32_t t, uint32_t next_round) {
   if (atomicMax(&a.qround[t], next_round) < next_round) {
     const uint32_t slot = atomicAdd(&a.cnt[next_round % 3], 1u);
@@ -71,138 +114,142 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
   __shared__ float Z[kFT * kFZ];
   __shared__ uint32_t chg[3];
   __shared__ uint32_t sides;
-  const int tid = threadIdx.x;
+  __shared__ uint32_t moved[kFT * kFT / 32];  // cells lowered during this visit
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int64_t H = a.H, W = a.W;
   if (!FIRST && blockIdx.x == 0 && tid == 0) a.cnt[(round + 2) % 3] = 0;
   const uint32_t n = FIRST ? (uint32_t)(a.TX * a.TY) : a.cnt[round % 3];
   if (n > 0 && blockIdx.x == 0 && tid == 0) atomicMax(&a.cnt[3], round + 1);
-  constexpr int KPT = kFT * kFT / kFThreads;
   for (uint32_t qi = blockIdx.x; qi < n; qi += gridDim.x) {
     const uint32_t t = FIRST ? qi : a.queue[round & 1][qi];
+    const uint64_t t_start = clock64();
+    (void)t_start;
     const int64_t ty = t / a.TX, tx = t - ty * a.TX;
     const int64_t y0 = ty * kFT, x0 = tx * kFT;
     const int th = (int)min((int64_t)kFT, H - y0), tw = (int)min((int64_t)kFT, W - x0);
-    uint32_t ik[KPT];  // keys at entry (change detection)
     if (tid == 0) {
       chg[0] = chg[1] = chg[2] = 0;
       sides = 0;
     }
-    if (FIRST) {
-      // z with its one-cell halo, as raw bits (NaN outside the DEM)
-      for (int i = tid; i < (kFT + 2) * (kFT + 2); i += kFThreads) {
-        const int r = i / (kFT + 2), c = i - r * (kFT + 2);
-        const int64_t gy = y0 - 1 + r, gx = x0 - 1 + c;
-        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
-        K[r * kFK + c] = in ? __float_as_uint(a.z[gy * W + gx]) : 0x7FC00000u;
-      }
-      __syncthreads();
+    if (tid < kFT * kFT / 32) moved[tid] = 0;
+    bool known = false;  // any key of the tile or its halo below +inf
+    {
+      float v[kHR], e[kHR];
+      load_halo_tile(FIRST ? a.z : a.F, y0, x0, H, W, v, e);
 #pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const int i = tid + k * kFThreads;
-        const int r = i / kFT, c = i - r * kFT;
+      for (int p = 0; p < kHR; ++p) {
+        const int r = 4 * p + w;
+        if (r >= kFT + 2) continue;
+        if (FIRST) {  // raw z bits for the seed test below
+          K[r * kFK + lane] = __float_as_uint(v[p]);
+          if (lane < 2) K[r * kFK + kFT + lane] = __float_as_uint(e[p]);
+        } else {
+          K[r * kFK + lane] = __builtin_isnan(v[p]) ? kKeyNone : fkey(v[p]);
+          if (lane < 2) K[r * kFK + kFT + lane] = __builtin_isnan(e[p]) ? kKeyNone : fkey(e[p]);
+          known |= !__builtin_isnan(v[p]) && v[p] != __builtin_inff();
+          known |= !__builtin_isnan(e[p]) && e[p] != __builtin_inff();
+        }
+      }
+    }
+    if (!FIRST) {
+      float zv[kTR];
+      const bool cx = lane < tw;
+      const float* p0 = a.z + (y0 + w) * W + x0 + lane;
+#pragma unroll
+      for (int p = 0; p < kTR; ++p) zv[p] = (cx && 4 * p + w < th) ? p0[(int64_t)(4 * p) * W] : __builtin_nanf("");
+#pragma unroll
+      for (int p = 0; p < kTR; ++p) Z[(4 * p + w) * kFZ + lane] = zv[p];
+    }
+    __syncthreads();
+    if (FIRST) {
+      // Seeds (valid, on the DEM boundary or next to NaN) start at z, every
+      // other valid cell at +inf; the halo ring knows only the DEM-boundary
+      // seeds (everything else there is unknown until the next round).
+      uint32_t ik[kTR];
+#pragma unroll
+      for (int p = 0; p < kTR; ++p) {
+        const int r = 4 * p + w, c = lane;
         const int h = (r + 1) * kFK + c + 1;
         const float zc = __uint_as_float(K[h]);
-        uint32_t key = kKeyInf;
+        uint32_t key = __builtin_isnan(zc) ? kKeyNone : kKeyInf;
         if (r < th && c < tw && !__builtin_isnan(zc)) {
           const int64_t gy = y0 + r, gx = x0 + c;
           bool seed = gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1;
-          if (!seed) {
-            const int nb[8] = {1, 1 - kFK, -kFK, -kFK - 1, -1, kFK - 1, kFK, kFK + 1};
-#pragma unroll
-            for (int d = 0; d < 8; ++d) seed |= __builtin_isnan(__uint_as_float(K[h + nb[d]]));
-          }
+          seed |= __builtin_isnan(__uint_as_float(K[h + 1])) || __builtin_isnan(__uint_as_float(K[h - 1])) ||
+                  __builtin_isnan(__uint_as_float(K[h - kFK - 1])) || __builtin_isnan(__uint_as_float(K[h - kFK])) ||
+                  __builtin_isnan(__uint_as_float(K[h - kFK + 1])) || __builtin_isnan(__uint_as_float(K[h + kFK - 1])) ||
+                  __builtin_isnan(__uint_as_float(K[h + kFK])) || __builtin_isnan(__uint_as_float(K[h + kFK + 1]));
           if (seed) key = fkey(zc);
         }
-        ik[k] = key;
+        ik[p] = key;
+        known |= key < kKeyInf;
         Z[r * kFZ + c] = zc;
       }
-      // halo ring: DEM-boundary cells are seeds; everything else is unknown
       uint32_t ring[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int j = tid + q * kFThreads;
-        ring[q] = kKeyInf;
+        ring[q] = kKeyNone;
         if (j < 4 * (kFT + 2) - 4) {
-          int r, c;
-          if (j < kFT + 2) { r = 0; c = j; }
-          else if (j < 2 * (kFT + 2)) { r = kFT + 1; c = j - (kFT + 2); }
-          else if (j < 3 * (kFT + 2) - 2) { r = j - 2 * (kFT + 2) + 1; c = 0; }
-          else { r = j - 3 * (kFT + 2) + 3; c = kFT + 1; }
+          const int h = ring_index(j);
+          const int r = h / kFK, c = h - r * kFK;
           const int64_t gy = y0 - 1 + r, gx = x0 - 1 + c;
-          const float v = __uint_as_float(K[r * kFK + c]);
-          if (!__builtin_isnan(v) && (gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1)) ring[q] = fkey(v);
+          const float v = __uint_as_float(K[h]);
+          if (!__builtin_isnan(v)) ring[q] = (gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1) ? fkey(v) : kKeyInf;
+          known |= ring[q] < kKeyInf;
         }
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const int i = tid + k * kFThreads;
-        K[(i / kFT + 1) * kFK + i % kFT + 1] = ik[k];
-      }
+      for (int p = 0; p < kTR; ++p) K[(4 * p + w + 1) * kFK + lane + 1] = ik[p];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int j = tid + q * kFThreads;
-        if (j < 4 * (kFT + 2) - 4) {
-          int r, c;
-          if (j < kFT + 2) { r = 0; c = j; }
-          else if (j < 2 * (kFT + 2)) { r = kFT + 1; c = j - (kFT + 2); }
-          else if (j < 3 * (kFT + 2) - 2) { r = j - 2 * (kFT + 2) + 1; c = 0; }
-          else { r = j - 3 * (kFT + 2) + 3; c = kFT + 1; }
-          K[r * kFK + c] = ring[q];
-        }
-      }
-    } else {
-      for (int i = tid; i < (kFT + 2) * (kFT + 2); i += kFThreads) {
-        const int r = i / (kFT + 2), c = i - r * (kFT + 2);
-        const int64_t gy = y0 - 1 + r, gx = x0 - 1 + c;
-        uint32_t key = kKeyInf;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-          const float f = a.F[gy * W + gx];
-          if (!__builtin_isnan(f)) key = fkey(f);
-        }
-        K[r * kFK + c] = key;
-      }
-#pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const int i = tid + k * kFThreads;
-        const int r = i / kFT, c = i - r * kFT;
-        Z[r * kFZ + c] = (r < th && c < tw) ? a.z[(y0 + r) * W + x0 + c] : __builtin_nanf("");
-      }
-      __syncthreads();
-#pragma unroll
-      for (int k = 0; k < KPT; ++k) {
-        const int i = tid + k * kFThreads;
-        ik[k] = K[(i / kFT + 1) * kFK + i % kFT + 1];
+        if (j < 4 * (kFT + 2) - 4) K[ring_index(j)] = ring[q];
       }
     }
-    __syncthreads();
+    // A tile whose cells and halo are all unknown (+inf) cannot change.
+    known = __syncthreads_or(known);
 
     // Directional sweeps until a full set of them changes nothing.
-    const int w = tid >> 6, lane = tid & 63;
     const float eps = a.eps;
     bool capped = false;
-    for (int it = 0;; ++it) {
+    int sets = 0;
+    for (int it = 0; known; ++it) {
+      ++sets;
       if (tid == 0) chg[(it + 1) % 3] = 0;
       bool any = false;
+      // One LDS round trip per step: the cell's key and its eight neighbours'
+      // are read together; z (read-only) is fetched one step ahead.
+      const int r0 = w == 0 ? 0 : w == 1 ? kFT - 1 : lane;
+      const int c0 = w == 2 ? 0 : w == 3 ? kFT - 1 : lane;
+      const int dh = w == 0 ? kFK : w == 1 ? -kFK : w == 2 ? 1 : -1;    // key step
+      const int dz = w == 0 ? kFZ : w == 1 ? -kFZ : w == 2 ? 1 : -1;    // z step
+      const bool along_rows = w < 2;
+      int h = (r0 + 1) * kFK + c0 + 1, hz = r0 * kFZ + c0;
+      float zn = Z[hz];
       for (int s = 0; s < kFT; ++s) {
-        const int r = w == 0 ? s : w == 1 ? kFT - 1 - s : lane;
-        const int c = w == 2 ? s : w == 3 ? kFT - 1 - s : lane;
-        if (r < th && c < tw) {
-          const float zc = Z[r * kFZ + c];
-          const int h = (r + 1) * kFK + c + 1;
+        const float zc = zn;
+        if (s + 1 < kFT) zn = Z[hz + dz];
+        const int r = along_rows ? (w == 0 ? s : kFT - 1 - s) : lane;
+        const int c = along_rows ? lane : (w == 2 ? s : kFT - 1 - s);
+        if (r < th && c < tw && !__builtin_isnan(zc)) {
           const uint32_t cur = K[h];
+          uint32_t m = min(min(K[h - kFK - 1], K[h - kFK]), min(K[h - kFK + 1], K[h - 1]));
+          m = min(min(m, kKeyInf), min(min(K[h + 1], K[h + kFK - 1]), min(K[h + kFK], K[h + kFK + 1])));
           const uint32_t kz = fkey(zc);
-          if (!__builtin_isnan(zc) && cur != kz) {
-            uint32_t m = min(min(K[h - kFK - 1], K[h - kFK]), min(K[h - kFK + 1], K[h - 1]));
-            m = min(m, min(min(K[h + 1], K[h + kFK - 1]), min(K[h + kFK], K[h + kFK + 1])));
+          if (cur != kz) {
             const uint32_t ki = fkey(inc_eps(fval(m), eps));
             const uint32_t nk = kz > ki ? kz : ki;
             if (nk < cur) {
               atomicMin(&K[h], nk);
+              atomicOr(&moved[(r * kFT + c) >> 5], 1u << (c & 31));
               any = true;
             }
           }
         }
+        h += dh;
+        hz += dz;
       }
       if (any) chg[it % 3] = 1;
       __syncthreads();
@@ -213,38 +260,58 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
       }
     }
 
-    // Write back what changed; note which neighbours see a changed cell.
+    // Write back (first round: everything; later: what moved) and note which
+    // neighbours hold a moved cell in their halo.
     uint32_t sb = 0;
+    {
+      float* p0 = a.F + (y0 + w) * W + x0 + lane;
+#pragma unroll 1
+      for (int p = 0; p < kTR; ++p) {
+        const int r = 4 * p + w, c = lane;
+        if (r >= th || c >= tw) continue;
+        const uint32_t key = K[(r + 1) * kFK + c + 1];
+        float* dst = p0 + (int64_t)(4 * p) * W;
+        // first round: every finite value is new to the neighbours
+        const bool mv = FIRST ? key < kKeyInf : (moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u;
+        if (FIRST) {
+          const float zc = Z[r * kFZ + c];
+          *dst = __builtin_isnan(zc) ? zc : fval(key);
+        } else if (mv) {
+          *dst = fval(key);
+        }
+        if (mv) {
+          if (r == 0 || c == 0 || r == th - 1 || c == tw - 1) {
+            // A neighbouring tile needs another visit only if this cell can
+            // lower one of its cells: the halo still holds their values from
+            // the start of this visit (an upper bound of their current ones).
+            const uint32_t ki = fkey(inc_eps(fval(key), a.eps));
 #pragma unroll
-    for (int k = 0; k < KPT; ++k) {
-      const int i = tid + k * kFThreads;
-      const int r = i / kFT, c = i - r * kFT;
-      if (r >= th || c >= tw) continue;
-      const uint32_t key = K[(r + 1) * kFK + c + 1];
-      const int64_t g = (y0 + r) * W + x0 + c;
-      if (FIRST) {
-        a.F[g] = __builtin_isnan(Z[r * kFZ + c]) ? Z[r * kFZ + c] : fval(key);
-      } else if (key != ik[k]) {
-        a.F[g] = fval(key);
-        const bool n_ = r == 0, s_ = r == th - 1, w_ = c == 0, e_ = c == tw - 1;
-        sb |= (n_ ? 1u : 0u) | (s_ ? 2u : 0u) | (w_ ? 4u : 0u) | (e_ ? 8u : 0u) |
-              (n_ && w_ ? 16u : 0u) | (n_ && e_ ? 32u : 0u) | (s_ && w_ ? 64u : 0u) | (s_ && e_ ? 128u : 0u);
+            for (int d = 0; d < 8; ++d) {
+              const int dr = d < 3 ? -1 : d < 5 ? 0 : 1;
+              const int dc = (d == 0 || d == 3 || d == 5) ? -1 : (d == 1 || d == 6) ? 0 : 1;
+              const int rq = r + dr, cq = c + dc;
+              if (rq >= 0 && rq < th && cq >= 0 && cq < tw) continue;  // inside this tile
+              const uint32_t kq = K[(rq + 1) * kFK + cq + 1];
+              if (kq == kKeyNone || kq <= ki) continue;
+              const int ny = rq < 0 ? 0 : rq >= th ? 2 : 1, nx = cq < 0 ? 0 : cq >= tw ? 2 : 1;
+              sb |= 1u << (ny * 3 + nx);
+            }
+          }
+        }
       }
     }
-    if (!FIRST && sb) atomicOr(&sides, sb);
+    if (sb) atomicOr(&sides, sb);
     __syncthreads();
-    if (FIRST || capped) {
-      // the halo was a guess, or the sweeps stopped early: once more
-      if (tid == 0) fill_enqueue(a, t, round + 1);
-    }
-    if (!FIRST && tid < 8) {
-      const uint32_t bits = sides;
-      const int dy[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
-      const int dx[8] = {0, 0, -1, 1, -1, 1, -1, 1};
-      const int64_t ny = ty + dy[tid], nx = tx + dx[tid];
-      if ((bits >> tid) & 1u && ny >= 0 && ny < a.TY && nx >= 0 && nx < a.TX)
+    // The sweeps stopped early: once more.  (A first-round tile whose halo
+    // guess was too high is queued by the neighbour that knows better.)
+    if (capped && tid == 0) fill_enqueue(a, t, round + 1);
+    if (tid < 9 && tid != 4) {
+      // bit 3*(dy+1) + (dx+1): the neighbouring tile at (dy, dx)
+      const int64_t ny = ty + tid / 3 - 1, nx = tx + tid % 3 - 1;
+      if ((sides >> tid) & 1u && ny >= 0 && ny < a.TY && nx >= 0 && nx < a.TX)
         fill_enqueue(a, (uint32_t)(ny * a.TX + nx), round + 1);
     }
+    D8_FILL_STAT(round, sets, t_start);
     __syncthreads();  // LDS is reused by the next tile
   }
 }
