@@ -120,7 +120,15 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
   if (!FIRST && blockIdx.x == 0 && tid == 0) a.cnt[(round + 2) % 3] = 0;
   const uint32_t n = FIRST ? (uint32_t)(a.TX * a.TY) : a.cnt[round % 3];
   if (n > 0 && blockIdx.x == 0 && tid == 0) atomicMax(&a.cnt[3], round + 1);
-  for (uint32_t qi = blockIdx.x; qi < n; qi += gridDim.x) {
+  // Tiles are handed out one at a time from a counter (visits differ a lot
+  // in cost; a static split would wait for the unluckiest workgroup).
+  __shared__ uint32_t grab;
+  if (blockIdx.x == 0 && tid == 0) a.cnt[4 + (round + 2) % 3] = 0;
+  for (;;) {
+    if (tid == 0) grab = atomicAdd(&a.cnt[4 + round % 3], 1u);
+    __syncthreads();
+    const uint32_t qi = grab;
+    if (qi >= n) break;
     const uint32_t t = FIRST ? qi : a.queue[round & 1][qi];
     const uint64_t t_start = clock64();
     (void)t_start;
@@ -320,14 +328,29 @@ __global__ void k_fill_reset(FillArgs a) {
   const int64_t nt = a.TX * a.TY;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nt; i += (int64_t)gridDim.x * blockDim.x)
     a.qround[i] = 0;
-  if (blockIdx.x == 0 && threadIdx.x < 4) a.cnt[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 8) a.cnt[threadIdx.x] = 0;
 }
 
 }  // namespace
 
+// As many workgroups as the chip holds at once (they then pull tiles from
+// the counter), never more than there are tiles.
+template <bool FIRST>
 static int fill_grid_blocks(int64_t ntiles) {
-  // four 34 KB workgroups fit one CU's LDS; one wave of them covers the chip
-  return (int)std::min<int64_t>(ntiles, 256 * 4);
+  static int per_chip[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (per_chip[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fill_round<FIRST>, kFThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
+        cus <= 0) {
+      per_cu = 4;
+      cus = 256;
+    }
+    per_chip[dev] = per_cu * cus;
+  }
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, per_chip[dev]));
 }
 
 hipError_t launch_fill_reset(const FillArgs& a, hipStream_t s) {
@@ -338,11 +361,12 @@ hipError_t launch_fill_reset(const FillArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fill_round(const FillArgs& a, uint32_t round, hipStream_t s) {
-  const int g = fill_grid_blocks(a.TX * a.TY);
   if (round == 0)
-    hipLaunchKernelGGL(k_fill_round<true>, dim3(g), dim3(kFThreads), 0, s, a, round);
+    hipLaunchKernelGGL(k_fill_round<true>, dim3(fill_grid_blocks<true>(a.TX * a.TY)), dim3(kFThreads), 0, s, a,
+                       round);
   else
-    hipLaunchKernelGGL(k_fill_round<false>, dim3(g), dim3(kFThreads), 0, s, a, round);
+    hipLaunchKernelGGL(k_fill_round<false>, dim3(fill_grid_blocks<false>(a.TX * a.TY)), dim3(kFThreads), 0, s,
+                       a, round);
   return hipGetLastError();
 }
 

@@ -74,8 +74,9 @@ hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float
 hipError_t launch_forward_resolve(const Plan& p, bool weighted, hipStream_t s);
 hipError_t launch_backward_resolve(const Plan& p, hipStream_t s);
 
-// Epsilon fill over 64x64 tiles.  Workspace: cnt (4 words: the queue lengths
-// of three rotating rounds, then the number of rounds that had work), qround
+// Epsilon fill over 64x64 tiles.  Workspace: cnt (words 0-2: the queue
+// lengths of three rotating rounds; 3: the number of rounds that had work;
+// 4-6: the rounds' tile-grab counters), qround
 // (per tile: the last round it was queued for) and two tile queues.
 constexpr int kFillTile = 64;
 struct FillArgs {
