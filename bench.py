@@ -93,7 +93,18 @@ def cpu_baseline(z_full, workload):
     oracle.accum_u32(d)
     dt = time.perf_counter() - t0
     return {"value": round(h * w / dt / 1e9, 5), "unit": "Gcells/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3), "host_nproc": os.cpu_count(), "host_cpu": host_cpu()}
+
+
+def host_cpu():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -156,6 +167,16 @@ def main():
     value = H * W / (ms_step * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Gcells/s (wall {wall:.2f}s)")
 
+    # Per-step spread: one pair of events around each step (a separate pass).
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a_, b_ in ev:
+        a_.record(stream)
+        d8.accum(dirs, tile=args.tile, out=out, ws=ws)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    per_step = sorted(a_.elapsed_time(b_) for a_, b_ in ev)
+    step_median, step_min = per_step[len(per_step) // 2], per_step[0]
+
     # Per-phase durations: the library records HIP events around each kernel
     # phase on the same stream (a separate pass of the same steps).
     d8.phase_timing(True)
@@ -183,7 +204,8 @@ def main():
                 "traffic": measured_traffic(dominant, args.workload, tile), "kernel": dominant}
     op_gbs = OP_BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9
 
-    extra = {"phase_ms": phase_ms, "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
+    extra = {"phase_ms": phase_ms, "step_ms_median": round(step_median, 4), "step_ms_min": round(step_min, 4),
+             "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
              "op_bytes_per_cell": OP_BYTES_PER_CELL, "wall_s": round(wall, 3)}
 
     if not args.no_fused:
