@@ -27,6 +27,7 @@
 // A cell already at z is final (values only fall and never below z), so
 // seeds and undisturbed terrain cost two LDS reads per visit.
 #include <algorithm>
+#include <atomic>
 
 #include "d8_internal.hpp"
 
@@ -337,10 +338,11 @@ __global__ void k_fill_reset(FillArgs a) {
 // the counter), never more than there are tiles.
 template <bool FIRST>
 static int fill_grid_blocks(int64_t ntiles) {
-  static int per_chip[64] = {0};
+  static std::atomic<int> per_chip[64];  // per device, 0 until queried (the same value from any thread)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
-  if (per_chip[dev] == 0) {
+  int n = per_chip[dev].load(std::memory_order_relaxed);
+  if (n == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_fill_round<FIRST>, kFThreads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu <= 0 ||
@@ -348,9 +350,10 @@ static int fill_grid_blocks(int64_t ntiles) {
       per_cu = 4;
       cus = 256;
     }
-    per_chip[dev] = per_cu * cus;
+    n = per_cu * cus;
+    per_chip[dev].store(n, std::memory_order_relaxed);
   }
-  return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, per_chip[dev]));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, n));
 }
 
 hipError_t launch_fill_reset(const FillArgs& a, hipStream_t s) {
