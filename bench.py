@@ -123,8 +123,8 @@ def main():
                     help="also run one 1 GiB device-to-device copy (profiler calibration of byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one MI355X only (the path is single-GPU; "
-              "see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only (the library runs the whole path on one device); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -56,7 +56,7 @@ typedef enum {
   D8_EHIP = 3,          /* a HIP runtime call or launch failed */
   D8_EBADDIR = 4,       /* device: bad direction code or target off-grid / into NoData */
   D8_ECYCLE = 5,        /* device: the direction field contains a cycle */
-  D8_EUNSUPPORTED = 6   /* combination not supported by this build */
+  D8_EUNSUPPORTED = 6   /* combination the library does not implement */
 } d8_status;
 
 enum { D8_E = 0, D8_NE, D8_N, D8_NW, D8_W, D8_SW, D8_S, D8_SE, D8_NONE = 8, D8_NODATA = 255 };

@@ -19,7 +19,7 @@
  *     up-slope area) evaluate Eq. (1) in dependency order; here they run on the
  *     whole DEM as one partition with a plain FIFO queue (Kahn's order).
  *
- * Readings where the paper is silent (each listed in the design doc):
+ * Readings where the paper is silent:
  *   - "lowest" neighbour, strict '<', scanned in the order E,NE,N,NW,W,SW,S,SE;
  *     the first minimum wins; no strictly lower neighbour -> outlet (code 8).
  *   - row 0 is north; E = (r, c+1), N = (r-1, c).
