@@ -31,9 +31,9 @@
  *   exception, d8_fill_eps, says so).
  *
  * Errors
- *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, unsupported
- *   tile, workspace too small, a HIP launch failure) are returned at once and
- *   nothing is enqueued.  Data errors found on the device (a direction code
+ *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, rows or cols
+ *   > 2^31-1, unsupported tile, workspace too small, a HIP launch failure)
+ *   are returned at once and nothing is enqueued.  Data errors found on the device (a direction code
  *   outside {0..8, 255}; a target off the grid or into NoData; a cycle) are
  *   OR-ed into a status word in the workspace; the computation still runs to
  *   completion and the outputs of affected cells are unspecified.  Read the

@@ -70,8 +70,10 @@ static int pick_threads(int ts, int waves, bool backward) {
   return nt;
 }
 
+// At most 2^32 - 1 cells (uint32 counts and cell numbering) and at most
+// 2^31 - 1 rows or columns (the kernels' DEM descriptor holds 32-bit sides).
 static bool shape_ok(int64_t rows, int64_t cols) {
-  return rows > 0 && cols > 0 && rows <= 0xFFFFFFFFll && cols <= 0xFFFFFFFFll &&
+  return rows > 0 && cols > 0 && rows <= 0x7FFFFFFFll && cols <= 0x7FFFFFFFll &&
          (uint64_t)rows * (uint64_t)cols <= 0xFFFFFFFFull;
 }
 

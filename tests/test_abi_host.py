@@ -42,6 +42,8 @@ def test_workspace_bytes_validation():
     assert L.d8_workspace_bytes(10, -1, 0) == 0
     assert L.d8_workspace_bytes(10, 10, 48) == 0
     assert L.d8_workspace_bytes(1 << 17, 1 << 16, 0) == 0          # > 2^32 - 1 cells
+    assert L.d8_workspace_bytes(1, 1 << 31, 0) == 0                # a side > 2^31 - 1
+    assert L.d8_workspace_bytes(65535, 65537, 0) > 0               # 2^32 - 1 cells
     a = L.d8_workspace_bytes(1000, 1000, 64)
     b = L.d8_workspace_bytes(1000, 1000, 32)
     assert 0 < a < b                                               # smaller tiles, more perimeter slots

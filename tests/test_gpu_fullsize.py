@@ -254,3 +254,57 @@ def test_c1_raw_fill_exact():
             near |= np.roll(np.roll(nan, dr, 0), dc, 1)
     seeds &= ~inner | near
     assert np.array_equal(dg == 8, seeds)
+
+
+# ------------------------------------------------- the largest shape accepted
+
+def identity_mismatches_chunked(dirs_t, A_t, rows=4096):
+    """identity_mismatches in row bands with a one-row halo (bounded memory)."""
+    H, W = dirs_t.shape
+    bad, outlet = 0, 0
+    for r0 in range(0, H, rows):
+        r1 = min(H, r0 + rows)
+        lo, hi = max(0, r0 - 1), min(H, r1 + 1)
+        d = dirs_t[lo:hi]
+        A = A_t[lo:hi].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        S = torch.zeros((hi - lo + 2, W + 2), dtype=torch.int64, device=A.device)
+        for k in range(8):
+            S[1 + DR[k]:hi - lo + 1 + DR[k], 1 + DC[k]:W + 1 + DC[k]] += torch.where(
+                d == k, A, torch.zeros((), dtype=torch.int64, device=A.device))
+        a, b = r0 - lo, r1 - lo
+        valid = (d[a:b] != 255).to(torch.int64)
+        bad += (A[a:b] != valid + S[1 + a:1 + b, 1:W + 1]).sum().item()
+        outlet += A[a:b][d[a:b] == 8].sum().item()
+        del S, A
+    return bad, outlet
+
+
+def test_counts_largest_shape_identity():
+    """rows * cols = 2^32 - 1, the largest grid the library accepts (uint32
+    counts and cell numbering): a tilted rough surface with NoData holes,
+    checked by the recursion identity at every cell and the outlet total."""
+    H, W = 65535, 65537
+    assert H * W == (1 << 32) - 1
+    say(f"largest shape {H}x{W}: surface")
+    g = torch.Generator(device=dev()).manual_seed(7)
+    z = torch.rand((H, W), generator=g, device=dev())
+    z.mul_(0.008)
+    z.add_(torch.arange(H, device=dev(), dtype=torch.float32).view(H, 1) * 0.01)
+    z.add_(torch.arange(W, device=dev(), dtype=torch.float32).view(1, W) * 0.01)
+    holes = torch.rand((H, W), generator=g, device=dev()) < 2e-6
+    z[holes] = float("nan")
+    del holes
+    dirs = d8.flowdirs(z)
+    nvalid = (dirs != 255).sum().item()
+    del z
+    torch.cuda.empty_cache()
+    say("accumulating")
+    A = d8.accum(dirs)
+    torch.cuda.synchronize()
+    assert d8.device_status() == d8.D8_OK
+    d8._ws_cache.clear()
+    torch.cuda.empty_cache()
+    say("identity check in bands")
+    bad, outlet = identity_mismatches_chunked(dirs, A)
+    assert bad == 0
+    assert outlet == nvalid
