@@ -276,14 +276,17 @@ def main():
         b = d8.Batch(shapes, dev)
         dp = d8.flowdirs_batched(b, b.pack([torch.from_numpy(x) for x in dems], torch.float32))
         cells4 = b.total
-        gr = d8.BatchedGraph(b)
+        wp4 = b.pack([torch.from_numpy(x) for x in ws4], torch.float32)
+        # the autotuner picks tile side and waves per tile (outside the timing)
+        t4, v4, tune_ms = d8.autotune_batched(b, dp, wp4)
+        gr = d8.BatchedGraph(b, tile=t4, waves=v4)
         gr.dirs.copy_(dp)
-        gr.w.copy_(b.pack([torch.from_numpy(x) for x in ws4], torch.float32))
+        gr.w.copy_(wp4)
         gr.g.copy_(b.pack([torch.from_numpy(x) for x in gs4], torch.float32))
         gr.capture()
         fwd_graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(fwd_graph):
-            d8.accum_batched(b, gr.dirs, gr.w, out=gr.area, ws=gr.ws)
+            d8.accum_batched(b, gr.dirs, gr.w, tile=t4, waves=v4, out=gr.area, ws=gr.ws)
         for _ in range(2):
             fwd_graph.replay()
             gr.replay()
@@ -302,6 +305,7 @@ def main():
         bf = c0.elapsed_time(c1_) / args.steps
         bfb = c1_.elapsed_time(c2) / args.steps
         extra["batched_graph"] = {"workload": f"{len(shapes)} DEMs, {cells4} cells (sides log-uniform 64..2048)",
+                                  "autotuned": {"tile": t4, "waves": v4, "fwd_bwd_ms": round(tune_ms, 4)},
                                   "fwd_gcells": round(cells4 / bf / 1e6, 2), "fwd_bwd_gcells": round(cells4 / bfb / 1e6, 2),
                                   "fwd_ms": round(bf, 4), "fwd_bwd_ms": round(bfb, 4), "ratio": round(bf / bfb, 4)}
         log(f"batched graph: {extra['batched_graph']}")
