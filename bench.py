@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-fill", action="store_true")
+    ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (profiler calibration of byte counters)")
     args = ap.parse_args()
@@ -310,6 +311,31 @@ def main():
                                   "fwd_ms": round(bf, 4), "fwd_bwd_ms": round(bfb, 4), "ratio": round(bf / bfb, 4)}
         log(f"batched graph: {extra['batched_graph']}")
         del gr, fwd_graph, dp
+
+    if not args.no_streamed:
+        # The same counts with the direction field and the counts in pinned
+        # host memory, streamed through the GPU in strips of 8192 rows: the
+        # PCIe-inclusive rate (14 B/cell cross the link: 1 + 4 out in the tile
+        # pass, 1 + 4 in and 4 out in the finalising pass).
+        dh = dirs.cpu().pin_memory()
+        oh = torch.empty((H, W), dtype=torch.uint32, pin_memory=True)
+        sr = min(8192, (H + 63) // 64 * 64)
+        wss = d8.workspace(d8.lib().d8_accum_streamed_workspace_bytes(H, W, sr), dev)
+        d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
+        ns = 2
+        t0 = time.perf_counter()
+        for _ in range(ns):
+            d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
+        st_ms = (time.perf_counter() - t0) * 1e3 / ns
+        same = bool(torch.equal(oh.view(torch.int32), out.cpu().view(torch.int32)))
+        extra["streamed"] = {"workload": f"{args.workload} direction field and counts in pinned host memory, "
+                                         f"strips of {sr} rows", "ms": round(st_ms, 2),
+                             "gcells": round(H * W / st_ms / 1e6, 3), "pcie_bytes_per_cell": 14,
+                             "pcie_gbs": round(14 * H * W / st_ms / 1e6, 1), "same_as_device": same}
+        log(f"streamed: {extra['streamed']}")
+        del dh, oh, wss
+        d8._ws_cache.clear()
+        torch.cuda.empty_cache()
 
     if not args.no_fill:
         # Conditioning before the method: the epsilon fill of the 8192^2 surface

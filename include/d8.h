@@ -27,8 +27,8 @@
  *   workspace of at least d8_*_workspace_bytes() bytes, 256-byte aligned.
  *   Outputs must not alias inputs.  Every call only enqueues work on `stream`
  *   (a hipStream_t; NULL = the default stream) and returns; there is no hidden
- *   synchronisation, so calls may be captured into a HIP graph (the one
- *   exception, d8_fill_eps, says so).
+ *   synchronisation, so calls may be captured into a HIP graph (the
+ *   exceptions, d8_fill_eps and d8_accum_streamed, say so).
  *
  * Errors
  *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, rows or cols
@@ -135,6 +135,26 @@ d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* di
 
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
+
+/* Up-slope counts of a direction field that stays in host memory (Sec. 4,
+ * Conclusions: on one node the method can keep intermediate results out of
+ * core and so handle DEMs larger than memory; here the per-tile perimeter
+ * records and the resolve stay on the device while the field and the counts
+ * stream through it).
+ * dirs_host: uint8 codes [rows*cols], out_host: uint32 [rows*cols] (output),
+ * both HOST pointers (pinned memory lets the copies run at full PCIe rate).
+ * strip_rows: rows per strip, a positive multiple of 64.  Row strips are
+ * copied to the device twice: once for the tile pass with unknown inflows
+ * (whose tile-local counts go back to out_host), once with those counts for
+ * the finalising pass.  ws: device workspace of
+ * d8_accum_streamed_workspace_bytes(rows, cols, strip_rows) bytes (the
+ * d8_workspace_bytes of the DEM at tile 64 plus two strip buffers, about
+ * 5 B per strip cell).  Same results and data-error reporting as d8_accum
+ * with unit weights, tile 64.  SYNCHRONISES `stream` before returning (the
+ * host buffers are in use until then). */
+size_t d8_accum_streamed_workspace_bytes(int64_t rows, int64_t cols, int64_t strip_rows);
+d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols, uint32_t* out_host,
+                            int64_t strip_rows, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Conditioning (Sec. 3 assumes the DEM is free of pits and flats before the

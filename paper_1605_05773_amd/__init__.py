@@ -56,6 +56,8 @@ def lib():
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
             "d8_accum_dem": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
+            "d8_accum_streamed_workspace_bytes": ([I64, I64, I64], SZ),
+            "d8_accum_streamed": ([P, I64, I64, P, I64, P, SZ, P], I32),
             "d8_fill_workspace_bytes": ([I64, I64], SZ),
             "d8_fill_eps": ([P, I64, I64, ctypes.c_float, P, P, SZ, P, P], I32),
             "d8_batched_workspace_bytes": ([P, I32, I32], SZ),
@@ -81,7 +83,7 @@ EXPORTED = (
     "d8_flowdirs", "d8_flowdirs_steepest", "d8_workspace_bytes", "d8_accum", "d8_accum_dem", "d8_accum_backward",
     "d8_batched_workspace_bytes", "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
-    "d8_fill_workspace_bytes", "d8_fill_eps",
+    "d8_fill_workspace_bytes", "d8_fill_eps", "d8_accum_streamed_workspace_bytes", "d8_accum_streamed",
 )
 NPHASES = 10
 
@@ -186,6 +188,31 @@ def accum_dem(dem: torch.Tensor, *, tile: int = 0, out: torch.Tensor | None = No
     _check(lib().d8_accum_dem(dem.data_ptr(), H, W, dirs.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(), tile,
                               _stream(dem.device)), "d8_accum_dem")
     return out, dirs
+
+
+def accum_streamed(dirs_host: torch.Tensor, *, strip_rows: int = 4096, out: torch.Tensor | None = None,
+                   device=None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """Up-slope counts of a direction field held in host memory (a CPU uint8
+    tensor, pinned for full PCIe rate): row strips of strip_rows rows (a
+    multiple of 64) stream through the GPU twice.  Returns uint32 counts in
+    host memory (pinned when allocated here).  Synchronises the stream."""
+    if not isinstance(dirs_host, torch.Tensor) or dirs_host.is_cuda or dirs_host.dtype != torch.uint8:
+        raise TypeError("dirs_host: expected a CPU uint8 tensor")
+    if dirs_host.dim() != 2 or not dirs_host.is_contiguous():
+        raise ValueError("dirs_host must be 2-D and contiguous")
+    H, W = dirs_host.shape
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint32, pin_memory=dirs_host.is_pinned())
+    elif out.is_cuda or out.dtype != torch.uint32 or out.shape != dirs_host.shape or not out.is_contiguous():
+        raise TypeError("out: expected a contiguous CPU uint32 tensor of the same shape")
+    nb = lib().d8_accum_streamed_workspace_bytes(H, W, strip_rows)
+    if nb == 0:
+        raise D8Error(D8_EINVAL, "d8_accum_streamed_workspace_bytes")
+    ws = workspace(nb, dev) if ws is None else ws
+    _check(lib().d8_accum_streamed(dirs_host.data_ptr(), H, W, out.data_ptr(), strip_rows, ws.data_ptr(), ws.numel(),
+                                   _stream(dev)), "d8_accum_streamed")
+    return out
 
 
 def fill(dem: torch.Tensor, eps: float = 1e-3, *, out: torch.Tensor | None = None,

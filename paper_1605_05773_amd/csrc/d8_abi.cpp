@@ -337,6 +337,65 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
   return run_backward(p, dirs, grad_out, grad_weights, 0, (hipStream_t)stream);
 }
 
+// ----------------------------------------------------------------- streamed --
+// Host-resident direction field and counts: row strips of `strip_rows` rows
+// pass through two device buffers, once for the tile pass with unknown
+// inflows and once for the finalising pass; the perimeter records and the
+// resolve stay on the device for the whole DEM.
+
+static size_t streamed_plan_bytes(int64_t rows, int64_t cols) { return d8_workspace_bytes(rows, cols, 64); }
+
+size_t d8_accum_streamed_workspace_bytes(int64_t rows, int64_t cols, int64_t strip_rows) {
+  if (!shape_ok(rows, cols) || strip_rows <= 0 || strip_rows % 64) return 0;
+  const int64_t sr = std::min<int64_t>(strip_rows, (rows + 63) / 64 * 64);
+  return streamed_plan_bytes(rows, cols) + align256((size_t)(sr + 2) * (size_t)cols) +
+         align256((size_t)sr * (size_t)cols * 4);
+}
+
+d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols, uint32_t* out_host,
+                            int64_t strip_rows, void* ws, size_t ws_bytes, void* stream) {
+  if (!dirs_host || !out_host) return D8_EINVAL;
+  const size_t need = d8_accum_streamed_workspace_bytes(rows, cols, strip_rows);
+  if (!need || !ws) return D8_EINVAL;
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
+  if (ws_bytes < need) return D8_ENOMEM;
+  const size_t pb = streamed_plan_bytes(rows, cols);
+  Plan p;
+  d8_status st = prep_single(p, rows, cols, ws, pb, 64);
+  if (st != D8_OK) return st;
+  if (p.bw != 64 || p.bh != 64) return D8_EUNSUPPORTED;  // blocks must be the tiles
+  const int64_t sr = std::min<int64_t>(strip_rows, (rows + 63) / 64 * 64);
+  uint8_t* dbuf = static_cast<uint8_t*>(ws) + pb;
+  uint32_t* obuf = reinterpret_cast<uint32_t*>(dbuf + align256((size_t)(sr + 2) * (size_t)cols));
+  const int64_t tx = (cols + 63) / 64;
+  hipStream_t s = (hipStream_t)stream;
+  if (launch_zero_header(p.hdr, s) != hipSuccess) return D8_EHIP;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      p.first = p.span = 0;
+      if (launch_forward_resolve(p, false, s) != hipSuccess) return D8_EHIP;
+    }
+    for (int64_t s0 = 0; s0 < rows; s0 += sr) {
+      const int64_t s1 = std::min(rows, s0 + sr);
+      const int64_t r0 = std::max<int64_t>(s0 - 1, 0), r1 = std::min(s1, rows - 1);  // rows with the halo
+      if (hipMemcpyAsync(dbuf, dirs_host + r0 * cols, (size_t)(r1 - r0 + 1) * (size_t)cols, hipMemcpyHostToDevice,
+                         s) != hipSuccess)
+        return D8_EHIP;
+      if (pass == 1 && hipMemcpyAsync(obuf, out_host + s0 * cols, (size_t)(s1 - s0) * (size_t)cols * 4,
+                                      hipMemcpyHostToDevice, s) != hipSuccess)
+        return D8_EHIP;
+      // the strip's tile rows; buffers addressed by global cell index
+      p.first = (s0 / 64) * tx;
+      p.span = ((s1 - s0 + 63) / 64) * tx;
+      if (launch_count_tiles(p, dbuf - r0 * cols, pass == 1, obuf - s0 * cols, 0, s) != hipSuccess) return D8_EHIP;
+      if (hipMemcpyAsync(out_host + s0 * cols, obuf, (size_t)(s1 - s0) * (size_t)cols * 4, hipMemcpyDeviceToHost,
+                         s) != hipSuccess)
+        return D8_EHIP;
+    }
+  }
+  return hipStreamSynchronize(s) == hipSuccess ? D8_OK : D8_EHIP;
+}
+
 // ------------------------------------------------------------- conditioning --
 
 static int64_t fill_tiles(int64_t rows, int64_t cols) {

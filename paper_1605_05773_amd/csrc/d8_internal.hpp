@@ -36,6 +36,9 @@ struct Plan {
   int bw = 0, bh = 0;  // workgroup block of the tile passes (whole tiles)
   int cpt = 16;        // cells per thread of the tile passes
   const float* dem = nullptr;  // fused call: codes computed from this DEM in the emit pass
+  // Streamed calls: when span > 0 the tile passes run only blocks (= tiles,
+  // for 64 x 64 tiles and blocks) first .. first + span - 1.
+  int64_t first = 0, span = 0;
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes

@@ -454,7 +454,7 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
     const uint8_t* __restrict__ dirs, const float* __restrict__ w, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, void* __restrict__ ex_val, void* __restrict__ out,
     float* __restrict__ out_lo, uint32_t* __restrict__ status, const float* __restrict__ dem,
-    uint8_t* __restrict__ dirs_out) {
+    uint8_t* __restrict__ dirs_out, int64_t first) {
   constexpr bool kCount = std::is_same<V, uint32_t>::value;
   using EV = std::conditional_t<kCount, uint64_t, double>;  // exit values for the resolve
   constexpr int NC = BW * BH;
@@ -463,7 +463,7 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
   constexpr int TPX = BW / TS, TPY = BH / TS;  // tiles per block row / column
   static_assert(TPX * TS == BW && TPY * TS == BH, "block of whole tiles");
   __shared__ DblSmem<BW, BH, V> sm;
-  const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
+  const BlockGeo g = block_geo<BW, BH, TS>(tab, first + xcd_tile(blockIdx.x, nblocks));
   const int tid = threadIdx.x;
   const int64_t W = g.dm.W;
   const int64_t base = g.dm.off + g.y0 * W + g.x0;  // the block's first cell
@@ -655,7 +655,7 @@ __device__ __forceinline__ int hoff(uint32_t d) {
 template <int TS, typename V>
 __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
                                                int cap, const void* __restrict__ F, void* __restrict__ out,
-                                               float* __restrict__ out_lo) {
+                                               float* __restrict__ out_lo, int64_t first) {
   constexpr bool kCount = std::is_same<V, uint32_t>::value;
   using FV = std::conditional_t<kCount, uint64_t, double>;  // resolved exit values
   constexpr int HS = TS + 2, NH = HS * HS, NC = TS * TS, NT = 256;
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   __shared__ V Y[NH];  // indexed like code (row stride HS)
   __shared__ int any;
   const int tid = threadIdx.x;
-  const TileGeo g = tile_geo(tab, xcd_tile(blockIdx.x, ntiles), TS);
+  const TileGeo g = tile_geo(tab, first + xcd_tile(blockIdx.x, ntiles), TS);
   D8_STAMP(1, 0);
   // Inflow of every receiver slot, resolved by the super-block pass.
   const FV* X = static_cast<const FV*>(F) + g.tile * cap;
@@ -1593,9 +1593,10 @@ template <int BW, int BH, int TS, typename V, int CPT>
 static hipError_t emit_cpt(const Plan& p, const uint8_t* dirs, const float* w, void* out, float* out_lo,
                            hipStream_t s) {
   constexpr int NT = BW * BH / CPT;
-  hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, w, p.tab,
-                     p.nblocks, p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr, p.dem,
-                     const_cast<uint8_t*>(dirs));
+  const int64_t nb = p.span ? p.span : p.nblocks;  // a run of blocks, or all
+  hipLaunchKernelGGL((k_block_emit<BW, BH, TS, V, CPT>), dim3((unsigned)nb), dim3(NT), 0, s, dirs, w, p.tab, nb,
+                     p.cap, p.ex_code, p.rl, (void*)p.ex_val, out, out_lo, p.hdr, p.dem,
+                     const_cast<uint8_t*>(dirs), p.span ? p.first : (int64_t)0);
   return hipGetLastError();
 }
 
@@ -1615,8 +1616,9 @@ static hipError_t emit_blk(const Plan& p, const uint8_t* dirs, const float* w, v
 template <int TS, typename V>
 static hipError_t fixup_ts(const Plan& p, const uint8_t* dirs, void* out, float* out_lo, hipStream_t s) {
   // the receiver inflows the super-block pass left in buf[2]
-  hipLaunchKernelGGL((k_fixup<TS, V>), dim3((unsigned)p.ntiles), dim3(256), 0, s, dirs, p.tab, p.ntiles, p.cap,
-                     (const void*)p.buf[2], out, out_lo);
+  const int64_t nt = p.span ? p.span : p.ntiles;  // a run of tiles, or all
+  hipLaunchKernelGGL((k_fixup<TS, V>), dim3((unsigned)nt), dim3(256), 0, s, dirs, p.tab, nt, p.cap,
+                     (const void*)p.buf[2], out, out_lo, p.span ? p.first : (int64_t)0);
   return hipGetLastError();
 }
 

@@ -105,3 +105,24 @@ def test_fill_argument_errors_before_device_work():
     assert f(fake, 100, 100, c(1e-3), ctypes.c_void_p(0x10000 + 400), ws, nb, None, None) == d8.D8_EINVAL
     assert f(fake, 100, 100, c(1e-3), out, ctypes.c_void_p(0x1000010), nb, None, None) == d8.D8_EINVAL
     assert f(fake, 100, 100, c(1e-3), out, ws, nb - 1, None, None) == d8.D8_ENOMEM
+
+
+def test_streamed_argument_errors_before_device_work():
+    L = d8.lib()
+    assert L.d8_accum_streamed_workspace_bytes(100, 100, 0) == 0
+    assert L.d8_accum_streamed_workspace_bytes(100, 100, 100) == 0      # not a multiple of 64
+    assert L.d8_accum_streamed_workspace_bytes(0, 100, 64) == 0
+    a = L.d8_accum_streamed_workspace_bytes(1000, 1000, 64)
+    b = L.d8_accum_streamed_workspace_bytes(1000, 1000, 256)
+    assert L.d8_workspace_bytes(1000, 1000, 64) < a < b
+    # a strip taller than the DEM is clipped to it
+    assert L.d8_accum_streamed_workspace_bytes(100, 100, 6400) == L.d8_accum_streamed_workspace_bytes(100, 100, 128)
+    host = (ctypes.c_uint8 * 16)()
+    out = (ctypes.c_uint32 * 16)()
+    ws = ctypes.c_void_p(0x1000000)
+    f = L.d8_accum_streamed
+    assert f(None, 4, 4, out, 64, ws, 1 << 30, None) == d8.D8_EINVAL
+    assert f(host, 4, 4, None, 64, ws, 1 << 30, None) == d8.D8_EINVAL
+    assert f(host, 4, 4, out, 32, ws, 1 << 30, None) == d8.D8_EINVAL
+    assert f(host, 4, 4, out, 64, ctypes.c_void_p(0x1000010), 1 << 30, None) == d8.D8_EINVAL
+    assert f(host, 4, 4, out, 64, ws, 16, None) == d8.D8_ENOMEM

@@ -141,6 +141,15 @@ def test_c1_flowdirs_and_counts_exact(c1):
     np.testing.assert_array_equal(got, oracle.accum_u32(d))
 
 
+def test_c1_streamed_exact(c1):
+    """The 8192^2 field with NoData held in pinned host memory, streamed in
+    strips of 1024 rows: counts equal the oracle's."""
+    _, d = c1
+    got = d8.accum_streamed(torch.from_numpy(d).pin_memory(), strip_rows=1024, device=dev())
+    assert d8.device_status() == d8.D8_OK
+    np.testing.assert_array_equal(got.view(torch.int32).numpy().view(np.uint32), oracle.accum_u32(d))
+
+
 def test_c1_weighted_and_backward(c1):
     _, d = c1
     w = demgen.lognormal_f32(d.shape, 303)
