@@ -314,15 +314,15 @@ def main():
 
     if not args.no_streamed:
         # The same counts with the direction field and the counts in pinned
-        # host memory, streamed through the GPU in strips of 8192 rows: the
+        # host memory, streamed through the GPU in strips of 2048 rows: the
         # PCIe-inclusive rate (14 B/cell cross the link: 1 + 4 out in the tile
         # pass, 1 + 4 in and 4 out in the finalising pass).
         dh = dirs.cpu().pin_memory()
         oh = torch.empty((H, W), dtype=torch.uint32, pin_memory=True)
-        sr = min(8192, (H + 63) // 64 * 64)
+        sr = min(2048, (H + 63) // 64 * 64)
         wss = d8.workspace(d8.lib().d8_accum_streamed_workspace_bytes(H, W, sr), dev)
         d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
-        ns = 2
+        ns = 3
         t0 = time.perf_counter()
         for _ in range(ns):
             d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)

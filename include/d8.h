@@ -146,12 +146,15 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
  * strip_rows: rows per strip, a positive multiple of 64.  Row strips are
  * copied to the device twice: once for the tile pass with unknown inflows
  * (whose tile-local counts go back to out_host), once with those counts for
- * the finalising pass.  ws: device workspace of
+ * the finalising pass.  The kernels run on `stream`; the copies run on two
+ * streams of the call's own (created and destroyed inside it, default
+ * priority), so the next strip's upload and the previous strip's download
+ * overlap the current strip's kernels.  ws: device workspace of
  * d8_accum_streamed_workspace_bytes(rows, cols, strip_rows) bytes (the
- * d8_workspace_bytes of the DEM at tile 64 plus two strip buffers, about
- * 5 B per strip cell).  Same results and data-error reporting as d8_accum
- * with unit weights, tile 64.  SYNCHRONISES `stream` before returning (the
- * host buffers are in use until then). */
+ * d8_workspace_bytes of the DEM at tile 64 plus two strip slots, about
+ * 10 B per strip-row cell).  Same results and data-error reporting as
+ * d8_accum with unit weights, tile 64.  SYNCHRONISES `stream` before
+ * returning (the host buffers are in use until then). */
 size_t d8_accum_streamed_workspace_bytes(int64_t rows, int64_t cols, int64_t strip_rows);
 d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols, uint32_t* out_host,
                             int64_t strip_rows, void* ws, size_t ws_bytes, void* stream);

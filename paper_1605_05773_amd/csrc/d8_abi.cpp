@@ -339,18 +339,44 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
 
 // ----------------------------------------------------------------- streamed --
 // Host-resident direction field and counts: row strips of `strip_rows` rows
-// pass through two device buffers, once for the tile pass with unknown
-// inflows and once for the finalising pass; the perimeter records and the
-// resolve stay on the device for the whole DEM.
+// pass through the device twice, once for the tile pass with unknown inflows
+// and once for the finalising pass; the perimeter records and the resolve
+// stay on the device for the whole DEM.  Two strip slots and two copy
+// streams (host to device, device to host) let the copies of neighbouring
+// strips run under the kernels of the current one and in both directions at
+// once; events order each slot's reuse.
 
 static size_t streamed_plan_bytes(int64_t rows, int64_t cols) { return d8_workspace_bytes(rows, cols, 64); }
+static size_t strip_dirs_bytes(int64_t sr, int64_t cols) { return align256((size_t)(sr + 2) * (size_t)cols); }
+static size_t strip_out_bytes(int64_t sr, int64_t cols) { return align256((size_t)sr * (size_t)cols * 4); }
 
 size_t d8_accum_streamed_workspace_bytes(int64_t rows, int64_t cols, int64_t strip_rows) {
   if (!shape_ok(rows, cols) || strip_rows <= 0 || strip_rows % 64) return 0;
   const int64_t sr = std::min<int64_t>(strip_rows, (rows + 63) / 64 * 64);
-  return streamed_plan_bytes(rows, cols) + align256((size_t)(sr + 2) * (size_t)cols) +
-         align256((size_t)sr * (size_t)cols * 4);
+  return streamed_plan_bytes(rows, cols) + 2 * (strip_dirs_bytes(sr, cols) + strip_out_bytes(sr, cols));
 }
+
+namespace {
+// Streams and events of one streamed call, released on every return path.
+struct StreamSet {
+  hipStream_t in = nullptr, out = nullptr;
+  hipEvent_t start = nullptr, pass1 = nullptr, last = nullptr;
+  hipEvent_t loaded[2] = {nullptr, nullptr}, done[2] = {nullptr, nullptr}, stored[2] = {nullptr, nullptr};
+  bool ok = true;
+  StreamSet() {
+    ok = hipStreamCreateWithFlags(&in, hipStreamNonBlocking) == hipSuccess &&
+         hipStreamCreateWithFlags(&out, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t* e : {&start, &pass1, &last, &loaded[0], &loaded[1], &done[0], &done[1], &stored[0], &stored[1]})
+      ok = ok && hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess;
+  }
+  ~StreamSet() {
+    for (hipEvent_t e : {start, pass1, last, loaded[0], loaded[1], done[0], done[1], stored[0], stored[1]})
+      if (e) (void)hipEventDestroy(e);
+    if (in) (void)hipStreamDestroy(in);
+    if (out) (void)hipStreamDestroy(out);
+  }
+};
+}  // namespace
 
 d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols, uint32_t* out_host,
                             int64_t strip_rows, void* ws, size_t ws_bytes, void* stream) {
@@ -365,35 +391,70 @@ d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols
   if (st != D8_OK) return st;
   if (p.bw != 64 || p.bh != 64) return D8_EUNSUPPORTED;  // blocks must be the tiles
   const int64_t sr = std::min<int64_t>(strip_rows, (rows + 63) / 64 * 64);
-  uint8_t* dbuf = static_cast<uint8_t*>(ws) + pb;
-  uint32_t* obuf = reinterpret_cast<uint32_t*>(dbuf + align256((size_t)(sr + 2) * (size_t)cols));
+  uint8_t* dbuf[2];
+  uint32_t* obuf[2];
+  {
+    uint8_t* b = static_cast<uint8_t*>(ws) + pb;
+    for (int i = 0; i < 2; ++i) {
+      dbuf[i] = b;
+      b += strip_dirs_bytes(sr, cols);
+      obuf[i] = reinterpret_cast<uint32_t*>(b);
+      b += strip_out_bytes(sr, cols);
+    }
+  }
   const int64_t tx = (cols + 63) / 64;
   hipStream_t s = (hipStream_t)stream;
-  if (launch_zero_header(p.hdr, s) != hipSuccess) return D8_EHIP;
+  StreamSet ss;
+  if (!ss.ok) return D8_EHIP;
+  // the workspace may still be in use by earlier work on `stream`
+  if (hipEventRecord(ss.start, s) != hipSuccess || hipStreamWaitEvent(ss.in, ss.start, 0) != hipSuccess ||
+      hipStreamWaitEvent(ss.out, ss.start, 0) != hipSuccess || launch_zero_header(p.hdr, s) != hipSuccess)
+    return D8_EHIP;
+  const auto fail = [&]() {
+    (void)hipStreamSynchronize(ss.in);
+    (void)hipStreamSynchronize(ss.out);
+    (void)hipStreamSynchronize(s);
+    return D8_EHIP;
+  };
   for (int pass = 0; pass < 2; ++pass) {
     if (pass == 1) {
       p.first = p.span = 0;
-      if (launch_forward_resolve(p, false, s) != hipSuccess) return D8_EHIP;
+      if (launch_forward_resolve(p, false, s) != hipSuccess) return fail();
+      // the finalising pass reads back the tile-local counts of the first
+      if (hipEventRecord(ss.pass1, ss.out) != hipSuccess || hipStreamWaitEvent(ss.in, ss.pass1, 0) != hipSuccess)
+        return fail();
     }
-    for (int64_t s0 = 0; s0 < rows; s0 += sr) {
+    int64_t strip = 0;
+    for (int64_t s0 = 0; s0 < rows; s0 += sr, ++strip) {
+      const int b = (int)(strip & 1);
       const int64_t s1 = std::min(rows, s0 + sr);
       const int64_t r0 = std::max<int64_t>(s0 - 1, 0), r1 = std::min(s1, rows - 1);  // rows with the halo
-      if (hipMemcpyAsync(dbuf, dirs_host + r0 * cols, (size_t)(r1 - r0 + 1) * (size_t)cols, hipMemcpyHostToDevice,
-                         s) != hipSuccess)
-        return D8_EHIP;
-      if (pass == 1 && hipMemcpyAsync(obuf, out_host + s0 * cols, (size_t)(s1 - s0) * (size_t)cols * 4,
-                                      hipMemcpyHostToDevice, s) != hipSuccess)
-        return D8_EHIP;
+      // slot b is free once the strip two back has been copied out
+      if (hipStreamWaitEvent(ss.in, ss.stored[b], 0) != hipSuccess ||
+          hipMemcpyAsync(dbuf[b], dirs_host + r0 * cols, (size_t)(r1 - r0 + 1) * (size_t)cols,
+                         hipMemcpyHostToDevice, ss.in) != hipSuccess)
+        return fail();
+      if (pass == 1 && hipMemcpyAsync(obuf[b], out_host + s0 * cols, (size_t)(s1 - s0) * (size_t)cols * 4,
+                                      hipMemcpyHostToDevice, ss.in) != hipSuccess)
+        return fail();
+      if (hipEventRecord(ss.loaded[b], ss.in) != hipSuccess || hipStreamWaitEvent(s, ss.loaded[b], 0) != hipSuccess)
+        return fail();
       // the strip's tile rows; buffers addressed by global cell index
       p.first = (s0 / 64) * tx;
       p.span = ((s1 - s0 + 63) / 64) * tx;
-      if (launch_count_tiles(p, dbuf - r0 * cols, pass == 1, obuf - s0 * cols, 0, s) != hipSuccess) return D8_EHIP;
-      if (hipMemcpyAsync(out_host + s0 * cols, obuf, (size_t)(s1 - s0) * (size_t)cols * 4, hipMemcpyDeviceToHost,
-                         s) != hipSuccess)
-        return D8_EHIP;
+      if (launch_count_tiles(p, dbuf[b] - r0 * cols, pass == 1, obuf[b] - s0 * cols, 0, s) != hipSuccess ||
+          hipEventRecord(ss.done[b], s) != hipSuccess || hipStreamWaitEvent(ss.out, ss.done[b], 0) != hipSuccess ||
+          hipMemcpyAsync(out_host + s0 * cols, obuf[b], (size_t)(s1 - s0) * (size_t)cols * 4, hipMemcpyDeviceToHost,
+                         ss.out) != hipSuccess ||
+          hipEventRecord(ss.stored[b], ss.out) != hipSuccess)
+        return fail();
     }
   }
-  return hipStreamSynchronize(s) == hipSuccess ? D8_OK : D8_EHIP;
+  if (hipEventRecord(ss.last, ss.out) != hipSuccess || hipStreamWaitEvent(s, ss.last, 0) != hipSuccess)
+    return fail();
+  const bool good = hipStreamSynchronize(ss.in) == hipSuccess && hipStreamSynchronize(ss.out) == hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess;
+  return good ? D8_OK : D8_EHIP;
 }
 
 // ------------------------------------------------------------- conditioning --
