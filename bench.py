@@ -209,6 +209,31 @@ def main():
              "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
              "op_bytes_per_cell": OP_BYTES_PER_CELL, "wall_s": round(wall, 3)}
 
+    if not args.no_streamed:
+        # The same counts with the direction field and the counts in pinned
+        # host memory, streamed through the GPU in strips of 2048 rows: the
+        # PCIe-inclusive rate (14 B/cell cross the link: 1 + 4 out in the tile
+        # pass, 1 + 4 in and 4 out in the finalising pass).
+        dh = dirs.cpu().pin_memory()
+        oh = torch.empty((H, W), dtype=torch.uint32, pin_memory=True)
+        sr = min(2048, (H + 63) // 64 * 64)
+        wss = d8.workspace(d8.lib().d8_accum_streamed_workspace_bytes(H, W, sr), dev)
+        d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
+        ns = 3
+        t0 = time.perf_counter()
+        for _ in range(ns):
+            d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
+        st_ms = (time.perf_counter() - t0) * 1e3 / ns
+        same = bool(torch.equal(oh.view(torch.int32), out.cpu().view(torch.int32)))
+        extra["streamed"] = {"workload": f"{args.workload} direction field and counts in pinned host memory, "
+                                         f"strips of {sr} rows", "ms": round(st_ms, 2),
+                             "gcells": round(H * W / st_ms / 1e6, 3), "pcie_bytes_per_cell": 14,
+                             "pcie_gbs": round(14 * H * W / st_ms / 1e6, 1), "same_as_device": same}
+        log(f"streamed: {extra['streamed']}")
+        del dh, oh, wss
+        d8._ws_cache.clear()
+        torch.cuda.empty_cache()
+
     if not args.no_fused:
         # End to end from the DEM: d8_flowdirs + d8_accum vs the fused
         # d8_accum_dem (codes computed inside the tile pass).
@@ -311,31 +336,6 @@ def main():
                                   "fwd_ms": round(bf, 4), "fwd_bwd_ms": round(bfb, 4), "ratio": round(bf / bfb, 4)}
         log(f"batched graph: {extra['batched_graph']}")
         del gr, fwd_graph, dp
-
-    if not args.no_streamed:
-        # The same counts with the direction field and the counts in pinned
-        # host memory, streamed through the GPU in strips of 2048 rows: the
-        # PCIe-inclusive rate (14 B/cell cross the link: 1 + 4 out in the tile
-        # pass, 1 + 4 in and 4 out in the finalising pass).
-        dh = dirs.cpu().pin_memory()
-        oh = torch.empty((H, W), dtype=torch.uint32, pin_memory=True)
-        sr = min(2048, (H + 63) // 64 * 64)
-        wss = d8.workspace(d8.lib().d8_accum_streamed_workspace_bytes(H, W, sr), dev)
-        d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
-        ns = 3
-        t0 = time.perf_counter()
-        for _ in range(ns):
-            d8.accum_streamed(dh, strip_rows=sr, out=oh, device=dev, ws=wss)
-        st_ms = (time.perf_counter() - t0) * 1e3 / ns
-        same = bool(torch.equal(oh.view(torch.int32), out.cpu().view(torch.int32)))
-        extra["streamed"] = {"workload": f"{args.workload} direction field and counts in pinned host memory, "
-                                         f"strips of {sr} rows", "ms": round(st_ms, 2),
-                             "gcells": round(H * W / st_ms / 1e6, 3), "pcie_bytes_per_cell": 14,
-                             "pcie_gbs": round(14 * H * W / st_ms / 1e6, 1), "same_as_device": same}
-        log(f"streamed: {extra['streamed']}")
-        del dh, oh, wss
-        d8._ws_cache.clear()
-        torch.cuda.empty_cache()
 
     if not args.no_fill:
         # Conditioning before the method: the epsilon fill of the 8192^2 surface
