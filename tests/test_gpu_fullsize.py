@@ -317,3 +317,83 @@ def test_counts_largest_shape_identity():
     bad, outlet = identity_mismatches_chunked(dirs, A)
     assert bad == 0
     assert outlet == nvalid
+
+
+# ------------------------------------------ conditioning at 32768^2 (properties)
+
+def _keys(f):
+    """Order-preserving int64 keys of float32 values (-0 below +0)."""
+    b = f.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    return torch.where(b >= 0x80000000, b ^ 0xFFFFFFFF, b | 0x80000000)
+
+
+def _unkey(k):
+    b = torch.where(k >= 0x80000000, k & 0x7FFFFFFF, k ^ 0xFFFFFFFF)
+    return (b - ((b >> 31) << 32)).to(torch.int32).view(torch.float32)
+
+
+def test_fill_32768_fixed_point():
+    """A 32768^2 tilted surface whose noise exceeds the tilt (pits and small
+    depressions everywhere) with NoData holes: the GPU fill satisfies the
+    defining equations at every cell, which have exactly one solution --
+    seeds keep z, every other valid cell equals max(z, min over valid
+    neighbours of inc(F)) in the total order of the float bits -- and
+    lowest-of-eight on it has outlets exactly at the seeds."""
+    n = 32768
+    eps = np.float32(1e-3)
+    g = torch.Generator(device=dev()).manual_seed(11)
+    say("fill 32768^2: surface")
+    z = torch.rand((n, n), generator=g, device=dev()).mul_(0.05)
+    z.add_(torch.arange(n, device=dev(), dtype=torch.float32).view(n, 1) * 0.01)
+    z.add_(torch.arange(n, device=dev(), dtype=torch.float32).view(1, n) * 0.01)
+    z[torch.rand((n, n), generator=g, device=dev()) < 2e-6] = float("nan")
+    say("GPU fill")
+    F, rounds = d8.fill(z, float(eps), return_rounds=True)
+    say(f"{rounds} rounds; checking the equations in bands")
+    d8._ws_cache.clear()
+    torch.cuda.empty_cache()
+    inf_key = int(_keys(torch.tensor([float("inf")], device=dev()))[0])
+    rows = 2048
+    for r0 in range(0, n, rows):
+        r1 = min(n, r0 + rows)
+        lo, hi = max(0, r0 - 1), min(n, r1 + 1)
+        zb, Fb = z[lo:hi], F[lo:hi]
+        assert torch.equal(torch.isnan(zb), torch.isnan(Fb))
+        K = torch.full((hi - lo + 2, n + 2), inf_key, dtype=torch.int64, device=dev())
+        kf = _keys(Fb)
+        K[1:-1, 1:-1] = torch.where(torch.isnan(Fb), torch.full_like(kf, inf_key), kf)
+        a, b = r0 - lo, r1 - lo
+        m = torch.full((b - a, n), inf_key, dtype=torch.int64, device=dev())
+        nanadj = torch.zeros((b - a, n), dtype=torch.bool, device=dev())
+        Zp = torch.full((hi - lo + 2, n + 2), float("nan"), device=dev())
+        Zp[1:-1, 1:-1] = zb
+        for dr, dc in zip(DR, DC):
+            m = torch.minimum(m, K[1 + a + dr:1 + b + dr, 1 + dc:n + 1 + dc])
+            nanadj |= torch.isnan(Zp[1 + a + dr:1 + b + dr, 1 + dc:n + 1 + dc])
+        del K, Zp
+        mv = _unkey(m)
+        y = mv + torch.tensor(eps, device=dev())
+        y = torch.where(y > mv, y, torch.nextafter(mv, torch.tensor(float("inf"), device=dev())))
+        zc, Fc = zb[a:b], Fb[a:b]
+        expect = _unkey(torch.maximum(_keys(zc), _keys(y)))
+        rr = torch.arange(r0, r1, device=dev()).view(-1, 1)
+        cc = torch.arange(n, device=dev()).view(1, -1)
+        seed = (rr == 0) | (rr == n - 1) | (cc == 0) | (cc == n - 1) | nanadj
+        valid = ~torch.isnan(zc)
+        want = torch.where(seed, zc, expect)
+        bad = valid & (want.view(torch.int32) != Fc.view(torch.int32))
+        assert not bad.any(), (r0, int(bad.sum()))
+    say("outlets of the filled surface")
+    dirs = d8.flowdirs(F)
+    valid = ~torch.isnan(z)
+    P = torch.zeros((n + 2, n + 2), dtype=torch.bool, device=dev())
+    P[1:-1, 1:-1] = torch.isnan(z)
+    nanadj = torch.zeros_like(valid)
+    for dr, dc in zip(DR, DC):
+        nanadj |= P[1 + dr:n + 1 + dr, 1 + dc:n + 1 + dc]
+    del P
+    edge = torch.zeros_like(valid)
+    edge[0] = edge[-1] = True
+    edge[:, 0] = edge[:, -1] = True
+    seeds = valid & (edge | nanadj)
+    assert torch.equal(dirs == 8, seeds)
