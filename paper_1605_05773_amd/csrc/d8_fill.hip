@@ -14,10 +14,12 @@
 // The fixed point is reached from above (F = +inf off the seeds) by chaotic
 // relaxation, which converges to the same unique point for any update order.
 // Work is organised as 64x64 tiles in LDS, the same partition-with-unknowns
-// idea as the accumulation: a tile relaxes to its own fixed point given the
-// current values of its one-cell halo, writes back what changed and, when a
-// perimeter cell changed, queues the neighbouring tiles whose halo holds that
-// cell for the next round.  Rounds repeat until no tile is queued.
+// idea as the accumulation: a tile visit relaxes the tile given the current
+// values of its one-cell halo, writes back what changed and queues for the
+// next round the neighbouring tiles a changed border cell can still lower,
+// and the tile itself while it is still changing.  Rounds repeat until no
+// tile is queued; then every tile is at its fixed point given its halo, and
+// the halos hold the final values, so the whole DEM is at the fixed point.
 //
 // Inside a tile the four waves of the workgroup sweep concurrently in the four
 // axis directions (rows down, rows up, columns right, columns left; one cell
@@ -46,7 +48,12 @@ constexpr int kFZ = kFT + 1;       // row stride of the elevation array (odd)
 constexpr int kFThreads = 256;     // four waves
 constexpr uint32_t kKeyInf = 0xFF800000u;   // key of +inf (a valid cell not reached yet)
 constexpr uint32_t kKeyNone = 0xFFFFFFFFu;  // no cell: outside the DEM or NaN (above every key)
-constexpr int kFillSweepCap = 255;         // sweep sets per tile visit
+// Extra sweep sets per tile visit.  With none, a visit runs one set and a
+// tile whose set changed anything simply goes round again: its next visit
+// also sees its neighbours' newer values, and no set is spent only to find
+// that nothing changes (8192^2 raw surface: 6.8 -> 4.7 ms against sweeping
+// each visit to its local fixed point).
+constexpr int kFillSweepCap = 0;
 
 __device__ __forceinline__ uint32_t fkey(float f) {
   const uint32_t u = __float_as_uint(f);
@@ -220,7 +227,8 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
     // A tile whose cells and halo are all unknown (+inf) cannot change.
     known = __syncthreads_or(known);
 
-    // Directional sweeps until a full set of them changes nothing.
+    // Directional sweeps: sets until one changes nothing, at most
+    // kFillSweepCap + 1 of them.
     const float eps = a.eps;
     bool capped = false;
     int sets = 0;
@@ -263,7 +271,7 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
       if (any) chg[it % 3] = 1;
       __syncthreads();
       if (!chg[it % 3]) break;
-      if (it == kFillSweepCap) {  // bounded work per visit: the tile goes round again
+      if (it == kFillSweepCap) {  // the tile goes round again
         capped = true;
         break;
       }
@@ -311,8 +319,9 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
     }
     if (sb) atomicOr(&sides, sb);
     __syncthreads();
-    // The sweeps stopped early: once more.  (A first-round tile whose halo
-    // guess was too high is queued by the neighbour that knows better.)
+    // The last set still changed something: once more.  (A first-round tile
+    // whose halo guess was too high is queued by the neighbour that knows
+    // better.)
     if (capped && tid == 0) fill_enqueue(a, t, round + 1);
     if (tid < 9 && tid != 4) {
       // bit 3*(dy+1) + (dx+1): the neighbouring tile at (dy, dx)
