@@ -499,7 +499,9 @@ d8_status d8_fill_eps(const float* dem, int64_t rows, int64_t cols, float eps, f
   const uint32_t kMaxFillRounds = 1u << 24;
   for (uint32_t r = 0;; ++r) {
     if (launch_fill_round(a, r, s) != hipSuccess) return D8_EHIP;
-    if (r == 0 || !(r <= 4 || r % 16 == 0)) continue;
+    // look after rounds 1, 2, 4, 8 and then every 8th (a look idles the GPU
+    // for a host round trip; a round past the end costs one empty launch)
+    if (r == 0 || !(r <= 8 ? (r & (r - 1)) == 0 : r % 8 == 0)) continue;
     uint32_t next = 0;
     if (hipMemcpyAsync(&next, a.cnt + (r + 1) % 3, sizeof(next), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

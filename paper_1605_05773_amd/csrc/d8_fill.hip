@@ -128,14 +128,13 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
   if (!FIRST && blockIdx.x == 0 && tid == 0) a.cnt[(round + 2) % 3] = 0;
   const uint32_t n = FIRST ? (uint32_t)(a.TX * a.TY) : a.cnt[round % 3];
   if (n > 0 && blockIdx.x == 0 && tid == 0) atomicMax(&a.cnt[3], round + 1);
-  // Tiles are handed out one at a time from a counter (visits differ a lot
-  // in cost; a static split would wait for the unluckiest workgroup).
+  // Tiles are handed out one at a time (visits differ a lot in cost; a
+  // static split would wait for the unluckiest workgroup): workgroup b takes
+  // entry b first, later ones come from a counter.  Workgroups beyond the
+  // queue's length leave without touching the counter.
   __shared__ uint32_t grab;
   if (blockIdx.x == 0 && tid == 0) a.cnt[4 + (round + 2) % 3] = 0;
-  for (;;) {
-    if (tid == 0) grab = atomicAdd(&a.cnt[4 + round % 3], 1u);
-    __syncthreads();
-    const uint32_t qi = grab;
+  for (uint32_t qi = blockIdx.x;;) {
     if (qi >= n) break;
     const uint32_t t = FIRST ? qi : a.queue[round & 1][qi];
     const uint64_t t_start = clock64();
@@ -330,7 +329,10 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         fill_enqueue(a, (uint32_t)(ny * a.TX + nx), round + 1);
     }
     D8_FILL_STAT(round, sets, t_start);
-    __syncthreads();  // LDS is reused by the next tile
+    if (tid == 0) grab = gridDim.x + atomicAdd(&a.cnt[4 + round % 3], 1u);
+    __syncthreads();  // also: LDS is reused by the next tile
+    qi = grab;
+    __syncthreads();  // every thread has read grab before it is written again
   }
 }
 
