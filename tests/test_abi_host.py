@@ -126,3 +126,13 @@ def test_streamed_argument_errors_before_device_work():
     assert f(host, 4, 4, out, 32, ws, 1 << 30, None) == d8.D8_EINVAL
     assert f(host, 4, 4, out, 64, ctypes.c_void_p(0x1000010), 1 << 30, None) == d8.D8_EINVAL
     assert f(host, 4, 4, out, 64, ws, 16, None) == d8.D8_ENOMEM
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
