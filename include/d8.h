@@ -23,7 +23,8 @@
  *
  * Ownership and ordering
  *   Every array argument is a DEVICE pointer owned by the caller (the library
- *   never allocates device memory).  Scratch memory is a caller-owned device
+ *   never allocates device memory), except the host arrays of
+ *   d8_accum_streamed.  Scratch memory is a caller-owned device
  *   workspace of at least d8_*_workspace_bytes() bytes, 256-byte aligned.
  *   Outputs must not alias inputs.  Every call only enqueues work on `stream`
  *   (a hipStream_t; NULL = the default stream) and returns; there is no hidden
@@ -33,11 +34,11 @@
  * Errors
  *   Argument errors (NULL pointers, rows*cols == 0 or > 2^32-1, rows or cols
  *   > 2^31-1, unsupported tile, workspace too small, a HIP launch failure)
- *   are returned at once and nothing is enqueued.  Data errors found on the device (a direction code
- *   outside {0..8, 255}; a target off the grid or into NoData; a cycle) are
- *   OR-ed into a status word in the workspace; the computation still runs to
- *   completion and the outputs of affected cells are unspecified.  Read the
- *   word with d8_device_status() after the call.
+ *   are returned at once and nothing is enqueued.  Data errors found on the
+ *   device (a direction code outside {0..8, 255}; a target off the grid or
+ *   into NoData; a cycle) are OR-ed into a status word in the workspace; the
+ *   computation still runs to completion and the outputs of affected cells
+ *   are unspecified.  Read the word with d8_device_status() after the call.
  */
 #ifndef D8_H_
 #define D8_H_
