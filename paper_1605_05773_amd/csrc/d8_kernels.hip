@@ -658,11 +658,13 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
                                                float* __restrict__ out_lo, int64_t first) {
   constexpr bool kCount = std::is_same<V, uint32_t>::value;
   using FV = std::conditional_t<kCount, uint64_t, double>;  // resolved exit values
-  constexpr int HS = TS + 2, NH = HS * HS, NC = TS * TS, NT = 256;
+  constexpr int NC = TS * TS, NT = 256;
   constexpr int NRX = (4 * TS - 4 + NT - 1) / NT;  // perimeter cells per thread
-  __shared__ __attribute__((aligned(4))) uint8_t code[NH];
-  __shared__ V Y[NH];  // indexed like code (row stride HS)
-  __shared__ int any;
+  // The tile's own codes and inflow sums only (row stride TS): a walk stops
+  // by its coordinates where its path leaves the tile, so no halo is kept,
+  // and for 64 x 64 counts the block fits eight to a CU's LDS.
+  __shared__ __attribute__((aligned(4))) uint8_t code[NC];
+  __shared__ V Y[NC];
   const int tid = threadIdx.x;
   const TileGeo g = tile_geo(tab, first + xcd_tile(blockIdx.x, ntiles), TS);
   D8_STAMP(1, 0);
@@ -680,7 +682,7 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
       int lr, lc;
       perim_cell(j, g.tw, g.th, lr, lc);
       xr[q] = (V)X[j];
-      hr[q] = (lr + 1) * HS + lc + 1;
+      hr[q] = lr * TS + lc;
     }
   }
   constexpr int KPT = NC / NT;
@@ -690,29 +692,23 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   using OV = std::conditional_t<kCount, uint32_t, float>;
   OV o[KPT];
   float l[KPT];
+  uint8_t cd[KPT];
   {
     const OV* O = static_cast<const OV*>(out) + base;
+    const uint8_t* D = dirs + base;
 #pragma unroll
     for (int k = 0; k < KPT; ++k) {
       const int i = tid + k * NT;
       const bool in = i / TS < g.th && i % TS < g.tw;
       o[k] = in ? O[(i / TS) * W + i % TS] : (OV)0;
       l[k] = (!kCount && out_lo && in) ? out_lo[base + (i / TS) * W + i % TS] : 0.0f;
+      cd[k] = in ? D[(i / TS) * W + i % TS] : kOutside;
     }
   }
-  load_halo<TS, TS, NT>(code, dirs, g.dm, g.y0, g.x0, g.tw);
-  for (int i = tid; i < NH; i += NT) Y[i] = 0;
-  if (tid == 0) any = 0;
-  __syncthreads();
-  // Fence the tile: the halo ring becomes kOutside, so a walk stops where its
-  // path leaves the tile (cells beyond the DEM already hold kOutside).
-  for (int i = tid; i < 4 * HS - 4; i += NT) {
-    int h;
-    if (i < HS) h = i;                                  // top row
-    else if (i < 2 * HS) h = (HS - 1) * HS + (i - HS);  // bottom row
-    else if (i < 3 * HS - 2) h = (i - 2 * HS + 1) * HS; // left column
-    else h = (i - 3 * HS + 4) * HS - 1;                 // right column
-    code[h] = kOutside;
+#pragma unroll
+  for (int k = 0; k < KPT; ++k) {
+    code[tid + k * NT] = cd[k];
+    Y[tid + k * NT] = 0;
   }
   __syncthreads();
   D8_STAMP(1, 1);
@@ -720,33 +716,25 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
 #pragma unroll
   for (int q = 0; q < NRX; ++q) {
     if (hr[q] < 0 || xr[q] == (V)0) continue;
-    any = 1;
     const V x = xr[q];
-    int h = hr[q];
+    int r = hr[q] / TS, c = hr[q] % TS;
     for (int n = 0; n < NC; ++n) {  // bounded: a cycle never ends
-      const uint32_t k = code[h];
-      if (k >= kOutside) break;  // left the tile, or a NoData target (flagged by the emit pass)
-      atomicAdd(&Y[h], x);
+      const uint32_t k = code[r * TS + c];
+      if (k >= kOutside) break;  // a NoData target (flagged by the emit pass)
+      atomicAdd(&Y[r * TS + c], x);
       if (k >= 8u) break;        // outlet (or an invalid code, flagged by the emit pass)
-      h += hoff<HS>(k);
+      r += ddr_t(k);
+      c += ddc_t(k);
+      if (r < 0 || r >= g.th || c < 0 || c >= g.tw) break;  // left the tile
     }
   }
   __syncthreads();
   D8_STAMP(1, 2);
-  if (!any) {
-    D8_STAMP(1, 3);
-    D8_STAMP(1, 4);
-    D8_STAMP(1, 5);
-    return;
-  }
   // The tile-local values written by the emit pass were fetched at the start
   // (their latency overlaps the walks); only the touched cells are stored.
   V y[KPT];
 #pragma unroll
-  for (int k = 0; k < KPT; ++k) {
-    const int i = tid + k * NT;
-    y[k] = Y[(i / TS + 1) * HS + i % TS + 1];
-  }
+  for (int k = 0; k < KPT; ++k) y[k] = Y[tid + k * NT];
   D8_STAMP(1, 3);
   if constexpr (kCount) {
     uint32_t* O = static_cast<uint32_t*>(out) + base;
