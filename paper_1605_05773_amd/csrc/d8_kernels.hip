@@ -652,6 +652,29 @@ __device__ __forceinline__ int hoff(uint32_t d) {
 // walks its path accumulating into an LDS array (paths may share cells; the
 // sums are exact for counts and fp64 for weights), then the touched cells of
 // the output are updated.
+// Walks of the finalising pass: each receiver q with inflow xr[q] adds it at
+// every cell of its in-tile path (row stride TS), atomically into Y.
+template <int TS, typename V, int NRX>
+__device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int (&hr)[NRX], const V (&xr)[NRX],
+                                            int th, int tw) {
+  constexpr int NC = TS * TS;
+#pragma unroll
+  for (int q = 0; q < NRX; ++q) {
+    if (hr[q] < 0 || xr[q] == (V)0) continue;
+    const V x = xr[q];
+    int r = hr[q] / TS, c = hr[q] % TS;
+    for (int n = 0; n < NC; ++n) {  // bounded: a cycle never ends
+      const uint32_t k = code[r * TS + c];
+      if (k >= kOutside) break;  // a NoData target (flagged by the emit pass)
+      atomicAdd(&Y[r * TS + c], x);
+      if (k >= 8u) break;        // outlet (or an invalid code, flagged by the emit pass)
+      r += ddr_t(k);
+      c += ddc_t(k);
+      if (r < 0 || r >= th || c < 0 || c >= tw) break;  // left the tile
+    }
+  }
+}
+
 template <int TS, typename V>
 __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs, DemTable tab, int64_t ntiles,
                                                int cap, const void* __restrict__ F, void* __restrict__ out,
@@ -663,8 +686,8 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   // The tile's own codes and inflow sums only (row stride TS): a walk stops
   // by its coordinates where its path leaves the tile, so no halo is kept,
   // and for 64 x 64 counts the block fits eight to a CU's LDS.
-  __shared__ __attribute__((aligned(4))) uint8_t code[NC];
-  __shared__ V Y[NC];
+  __shared__ __attribute__((aligned(16))) uint8_t code[NC];
+  __shared__ __attribute__((aligned(16))) V Y[NC];
   const int tid = threadIdx.x;
   const TileGeo g = tile_geo(tab, first + xcd_tile(blockIdx.x, ntiles), TS);
   D8_STAMP(1, 0);
@@ -689,6 +712,50 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   static_assert(KPT * NT == NC, "whole tile per pass");
   const int64_t base = g.dm.off + g.y0 * g.dm.W + g.x0;
   const int64_t W = g.dm.W;
+  // Counts on a whole 64 x 64 tile whose rows are 4-cell aligned: each thread
+  // moves groups of 4 cells (one 32-bit word of codes, one 16-byte vector of
+  // values) instead of single cells.
+  if constexpr (kCount && TS == 64) {
+    constexpr int GPR = TS / 4, KG = NC / 4 / NT;  // groups per row, per thread
+    if (g.tw == TS && g.th == TS && ((base | W) & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(dirs) & 3) == 0) {
+      const uint32_t* D = reinterpret_cast<const uint32_t*>(dirs + base);
+      uint32_t* O = static_cast<uint32_t*>(out) + base;
+      uint32_t cw[KG];
+      uint4 o4[KG];
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
+        cw[q] = D[(r * W + c4) / 4];
+        o4[q] = *reinterpret_cast<const uint4*>(O + r * W + c4);
+      }
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        const int j = tid + q * NT;
+        reinterpret_cast<uint32_t*>(code)[j] = cw[q];
+        reinterpret_cast<uint4*>(Y)[j] = make_uint4(0u, 0u, 0u, 0u);
+      }
+      __syncthreads();
+      D8_STAMP(1, 1);
+      fixup_walks<TS, V, NRX>(code, Y, hr, xr, g.th, g.tw);
+      __syncthreads();
+      D8_STAMP(1, 2);
+#pragma unroll
+      for (int q = 0; q < KG; ++q) {
+        const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
+        const uint4 y = reinterpret_cast<const uint4*>(Y)[j];
+        uint32_t* o = O + r * W + c4;
+        if (y.x) o[0] = o4[q].x + y.x;
+        if (y.y) o[1] = o4[q].y + y.y;
+        if (y.z) o[2] = o4[q].z + y.z;
+        if (y.w) o[3] = o4[q].w + y.w;
+      }
+      D8_STAMP(1, 3);
+      D8_STAMP(1, 4);
+      D8_STAMP(1, 5);
+      return;
+    }
+  }
   using OV = std::conditional_t<kCount, uint32_t, float>;
   OV o[KPT];
   float l[KPT];
@@ -713,21 +780,7 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   __syncthreads();
   D8_STAMP(1, 1);
   // Walks: add the inflow at every cell of the receiver's in-tile path.
-#pragma unroll
-  for (int q = 0; q < NRX; ++q) {
-    if (hr[q] < 0 || xr[q] == (V)0) continue;
-    const V x = xr[q];
-    int r = hr[q] / TS, c = hr[q] % TS;
-    for (int n = 0; n < NC; ++n) {  // bounded: a cycle never ends
-      const uint32_t k = code[r * TS + c];
-      if (k >= kOutside) break;  // a NoData target (flagged by the emit pass)
-      atomicAdd(&Y[r * TS + c], x);
-      if (k >= 8u) break;        // outlet (or an invalid code, flagged by the emit pass)
-      r += ddr_t(k);
-      c += ddc_t(k);
-      if (r < 0 || r >= g.th || c < 0 || c >= g.tw) break;  // left the tile
-    }
-  }
+  fixup_walks<TS, V, NRX>(code, Y, hr, xr, g.th, g.tw);
   __syncthreads();
   D8_STAMP(1, 2);
   // The tile-local values written by the emit pass were fetched at the start
