@@ -114,6 +114,17 @@ def test_counts_c0_like_nodata_and_ragged():
         np.testing.assert_array_equal(gpu_counts(d, t), ref)
 
 
+@pytest.mark.parametrize("shape", [(256, 320), (200, 260), (192, 258), (131, 516)])
+def test_counts_fixup_grouped_and_single_paths(shape):
+    """The finalising pass moves counts 4 cells at a time on whole 64x64
+    tiles whose rows start on a 4-cell boundary and cell by cell elsewhere:
+    all tiles grouped (256x320), grouped and ragged tiles mixed (200x260,
+    131x516), no row aligned (192x258).  Both give the oracle's counts."""
+    z = demgen.fbm_dem(*shape, sigma=5.0, seed=sum(shape), nodata_frac=0.02, nodata_seed=3)
+    d = oracle.flowdirs(z)
+    np.testing.assert_array_equal(gpu_counts(d, 64), oracle.accum_u32(d))
+
+
 def test_counts_deterministic_and_tile_invariant():
     d = oracle.flowdirs(demgen.fbm_dem(777, 1000, sigma=5.0, seed=9))
     runs = [gpu_counts(d, t) for t in (32, 64, 64, 128)]
