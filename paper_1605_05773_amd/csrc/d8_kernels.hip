@@ -712,28 +712,40 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
   static_assert(KPT * NT == NC, "whole tile per pass");
   const int64_t base = g.dm.off + g.y0 * g.dm.W + g.x0;
   const int64_t W = g.dm.W;
-  // Counts on a whole 64 x 64 tile whose rows are 4-cell aligned: each thread
-  // moves groups of 4 cells (one 32-bit word of codes, one 16-byte vector of
-  // values) instead of single cells.
-  if constexpr (kCount && TS == 64) {
+  // A whole 64 x 64 tile whose rows are 4-cell aligned: each thread moves
+  // groups of 4 cells (one 32-bit word of codes, one 16-byte vector of output
+  // values, and of low parts for weights) instead of single cells.
+  if constexpr (TS == 64) {
     constexpr int GPR = TS / 4, KG = NC / 4 / NT;  // groups per row, per thread
-    if (g.tw == TS && g.th == TS && ((base | W) & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 &&
+    const uintptr_t al = reinterpret_cast<uintptr_t>(out) | (kCount ? 0 : reinterpret_cast<uintptr_t>(out_lo));
+    if (g.tw == TS && g.th == TS && ((base | W) & 3) == 0 && (al & 15) == 0 &&
         (reinterpret_cast<uintptr_t>(dirs) & 3) == 0) {
+      using OV4 = std::conditional_t<kCount, uint4, float4>;
+      using OS = std::conditional_t<kCount, uint32_t, float>;
       const uint32_t* D = reinterpret_cast<const uint32_t*>(dirs + base);
-      uint32_t* O = static_cast<uint32_t*>(out) + base;
+      OS* O = static_cast<OS*>(out) + base;
+      float* L = (!kCount && out_lo) ? out_lo + base : nullptr;
       uint32_t cw[KG];
-      uint4 o4[KG];
+      OV4 o4[KG];
+      float4 l4[kCount ? 1 : KG];
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
         const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
         cw[q] = D[(r * W + c4) / 4];
-        o4[q] = *reinterpret_cast<const uint4*>(O + r * W + c4);
+        o4[q] = *reinterpret_cast<const OV4*>(O + r * W + c4);
+        if constexpr (!kCount)
+          l4[q] = L ? *reinterpret_cast<const float4*>(L + r * W + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
         const int j = tid + q * NT;
         reinterpret_cast<uint32_t*>(code)[j] = cw[q];
-        reinterpret_cast<uint4*>(Y)[j] = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (kCount) {
+          reinterpret_cast<uint4*>(Y)[j] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+          reinterpret_cast<double2*>(Y)[2 * j] = make_double2(0.0, 0.0);
+          reinterpret_cast<double2*>(Y)[2 * j + 1] = make_double2(0.0, 0.0);
+        }
       }
       __syncthreads();
       D8_STAMP(1, 1);
@@ -743,12 +755,29 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
         const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
-        const uint4 y = reinterpret_cast<const uint4*>(Y)[j];
-        uint32_t* o = O + r * W + c4;
-        if (y.x) o[0] = o4[q].x + y.x;
-        if (y.y) o[1] = o4[q].y + y.y;
-        if (y.z) o[2] = o4[q].z + y.z;
-        if (y.w) o[3] = o4[q].w + y.w;
+        const int64_t e = r * W + c4;
+        if constexpr (kCount) {
+          const uint4 y = reinterpret_cast<const uint4*>(Y)[j];
+          if (y.x) O[e + 0] = o4[q].x + y.x;
+          if (y.y) O[e + 1] = o4[q].y + y.y;
+          if (y.z) O[e + 2] = o4[q].z + y.z;
+          if (y.w) O[e + 3] = o4[q].w + y.w;
+        } else {
+          const double2 ya = reinterpret_cast<const double2*>(Y)[2 * j];
+          const double2 yb = reinterpret_cast<const double2*>(Y)[2 * j + 1];
+          const double y[4] = {ya.x, ya.y, yb.x, yb.y};
+          const float ov[4] = {o4[q].x, o4[q].y, o4[q].z, o4[q].w};
+          const float lv[4] = {l4[q].x, l4[q].y, l4[q].z, l4[q].w};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (y[t] != 0.0) {
+              const double x = (double)ov[t] + (double)lv[t] + y[t];
+              const float hi = (float)x;
+              O[e + t] = hi;
+              if (L) L[e + t] = (float)(x - (double)hi);
+            }
+          }
+        }
       }
       D8_STAMP(1, 3);
       D8_STAMP(1, 4);
