@@ -96,6 +96,33 @@ def cpu_baseline(z_full, workload):
             "seconds": round(dt, 3), "host_nproc": os.cpu_count(), "host_cpu": host_cpu()}
 
 
+def identity_check(dirs, counts, rows=4096):
+    """Cells where counts != [valid] + sum of counts over the cells draining in,
+    and the sum of counts over outlet cells (int64 torch ops on the device, in
+    row bands with a one-row halo)."""
+    import torch
+
+    dr = (0, -1, -1, -1, 0, 1, 1, 1)
+    dc = (1, 1, 0, -1, -1, -1, 0, 1)
+    H, W = dirs.shape
+    bad, outlet = 0, 0
+    for r0 in range(0, H, rows):
+        r1 = min(H, r0 + rows)
+        lo, hi = max(0, r0 - 1), min(H, r1 + 1)
+        d = dirs[lo:hi]
+        A = counts[lo:hi].view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+        S = torch.zeros((hi - lo + 2, W + 2), dtype=torch.int64, device=A.device)
+        zero = torch.zeros((), dtype=torch.int64, device=A.device)
+        for k in range(8):
+            S[1 + dr[k]:hi - lo + 1 + dr[k], 1 + dc[k]:W + 1 + dc[k]] += torch.where(d == k, A, zero)
+        a, b = r0 - lo, r1 - lo
+        valid = (d[a:b] != 255).to(torch.int64)
+        bad += int((A[a:b] != valid + S[1 + a:1 + b, 1:W + 1]).sum().item())
+        outlet += int(A[a:b][d[a:b] == 8].sum().item())
+        del S, A
+    return bad, outlet
+
+
 def host_cpu():
     try:
         with open("/proc/cpuinfo") as f:
@@ -168,6 +195,16 @@ def main():
     value = H * W / (ms_step * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {value:.1f} Gcells/s (wall {wall:.2f}s)")
 
+    # The timed output, checked once outside the timed region: on a D8 forest
+    # the recursion of Eq. (1) has exactly one solution, so an exact integer
+    # check at every cell plus the outlet total proves the counts.
+    bad, outlet = identity_check(dirs, out)
+    nvalid = int((dirs != 255).sum().item())
+    if bad or outlet != nvalid:
+        raise SystemExit(f"timed output fails the Eq. (1) identity at {bad} cells "
+                         f"(outlet total {outlet} vs {nvalid} valid cells)")
+    log("timed output verified: Eq. (1) identity at every cell, outlet total = valid cells")
+
     # Per-step spread: one pair of events around each step (a separate pass).
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for a_, b_ in ev:
@@ -205,7 +242,8 @@ def main():
                 "traffic": measured_traffic(dominant, args.workload, tile), "kernel": dominant}
     op_gbs = OP_BYTES_PER_CELL * cells / (ms_step * 1e-3) / 1e9
 
-    extra = {"phase_ms": phase_ms, "step_ms_median": round(step_median, 4), "step_ms_min": round(step_min, 4),
+    extra = {"verified": True, "verification": "Eq. (1) identity at every cell and outlet total, on the timed output",
+             "phase_ms": phase_ms, "step_ms_median": round(step_median, 4), "step_ms_min": round(step_min, 4),
              "op_roofline_frac": round(op_gbs / HBM_PEAK_GBS, 4),
              "op_bytes_per_cell": OP_BYTES_PER_CELL, "wall_s": round(wall, 3)}
 

@@ -66,8 +66,8 @@ typedef enum { D8_U32 = 0, D8_F32 = 1 } d8_dtype;
 
 /* One DEM of a batch: element offset of its first cell in the packed buffers
  * (the same offset is used for dem, dirs, weights, outputs and gradients) and
- * its shape.  Host array for *_workspace_bytes and d8_plan_*, device array for
- * the batched launches. */
+ * its shape.  Host array for d8_batched_workspace_bytes and the host_desc
+ * arguments, device array for the dev_desc arguments of the batched launches. */
 typedef struct {
   int64_t offset;
   int32_t rows;
@@ -109,21 +109,16 @@ size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile);
  * weights: float32 [rows*cols], or NULL for unit weights.
  * out_dtype: D8_U32 (counts; requires weights == NULL) or D8_F32.
  * out: uint32 or float32 [rows*cols] (output).  NoData cells get 0.
- *   Counts are exact.  Weighted sums are carried as float32 pairs (hi, lo)
- *   with error-free transformations inside tiles and in fp64 across tiles;
- *   out = fl32(hi + lo).
- * out_lo: NULL, or float32 [rows*cols] receiving the rounding residual, so
- *   that out + out_lo carries about 48 significant bits (weighted only).
+ *   Counts are exact.  Weighted sums are accumulated in fp64 (inside tiles
+ *   and across tiles); out = RN32(sum).
+ * out_lo: NULL, or float32 [rows*cols] receiving RN32(sum - out), so that
+ *   out + out_lo carries about 48 significant bits of the fp64 sum (weighted
+ *   only).
  * ws / ws_bytes: workspace.  tile: 0, 32, 64 or 128. */
 d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights,
                    d8_dtype out_dtype, void* out, float* out_lo, void* ws, size_t ws_bytes, int tile,
                    void* stream);
 
-/* Adjoint of the weighted accumulation.  The map w -> A is linear,
- * A = (I - P)^-1 w with P the D8 drainage matrix, so for a loss with
- * dL/dA = grad_out the gradient is grad_weights = (I - P)^-T grad_out:
- * grad_weights(c) = sum of grad_out over the cells on c's downstream path,
- * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0. */
 /* Fused flow directions and counts: dem (float32, NaN = NoData) -> dirs and
  * out, equal to d8_flowdirs followed by d8_accum with unit weights and
  * D8_U32 output.  The tile pass computes each tile's codes from the DEM
@@ -134,6 +129,11 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
 d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, uint32_t* out, void* ws,
                        size_t ws_bytes, int tile, void* stream);
 
+/* Adjoint of the weighted accumulation.  The map w -> A is linear,
+ * A = (I - P)^-1 w with P the D8 drainage matrix, so for a loss with
+ * dL/dA = grad_out the gradient is grad_weights = (I - P)^-T grad_out:
+ * grad_weights(c) = sum of grad_out over the cells on c's downstream path,
+ * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0. */
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
 

@@ -105,6 +105,36 @@ def test_counts_32768_identity():
     assert torch.equal(A2.view(torch.int32), A.view(torch.int32))
 
 
+@pytest.mark.timeout(900)
+def test_counts_c2a_workload_exact():
+    """The benchmarked workload itself: the 32768^2 fBm DEM (sigma 50 m,
+    Hurst 0.7, tilt 0.01, eps-filled), default tile, as bench.py times it.
+    Flow directions and counts are compared with the oracle at every cell,
+    and the recursion identity and the outlet total are checked on the GPU."""
+    say("c2a: generating (or loading) the 32768^2 DEM")
+    z = demgen.config_dem("c2a")
+    zt = to_dev(z)
+    dirs = d8.flowdirs(zt)
+    del zt
+    say("c2a: accumulating (default tile)")
+    A = d8.accum(dirs)
+    torch.cuda.synchronize()
+    assert d8.device_status() == d8.D8_OK
+    say("c2a: identity check")
+    bad, A64 = identity_mismatches(dirs, A)
+    assert bad == 0
+    assert outlet_total(dirs, A64) == dirs.numel()
+    del A64
+    torch.cuda.empty_cache()
+    say("c2a: oracle flow directions")
+    dref = oracle.flowdirs(z)
+    del z
+    np.testing.assert_array_equal(to_np(dirs), dref)
+    say("c2a: oracle counts")
+    ref = oracle.accum_u32(dref)
+    assert np.array_equal(to_np(A), ref)
+
+
 def test_counts_serpentine_16384_closed_forms():
     n = 16384
     say("serpentine 16384^2")
@@ -186,7 +216,7 @@ def test_c3_gauges_targets_and_finite_differences():
     d8.accum(dd, to_dev(w), out=out, out_lo=lo)
     A_gpu = to_np(out)
     assert_rel(A_gpu, Aw, 1e-6, "c3 forward")
-    # residuals from the double-float pair (the pair carries ~48 bits)
+    # residuals from (out, out_lo): RN32(sum) and RN32(sum - out) of the fp64 sum
     Ag = to_np(out).astype(np.float64).ravel()[gauges] + to_np(lo).astype(np.float64).ravel()[gauges]
     resid = Ag - tg
     gL = np.zeros(d.size, np.float64)

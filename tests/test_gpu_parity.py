@@ -1,9 +1,9 @@
 """GPU parity: the HIP library (through its C ABI) against the CPU oracle.
 
 Counts and flow directions must match bit for bit; weighted results and
-gradients within 1e-6 relative of fp64 (the bound of the benchmark spec's target;
-the tile passes carry float32 pairs with about 48 significant bits and the
-resolve runs in fp64, so the observed error is far below it).
+gradients within 1e-6 relative of fp64 (the tolerance the method's weighted
+form is held to; the tile passes and the resolve sum in fp64 and round once to
+float32, so the observed error is far below it).
 """
 import numpy as np
 import pytest
