@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libd8.so")
-SOURCES = ["d8_kernels.hip", "d8_fill.hip", "d8_abi.cpp"]
+SOURCES = ["d8_kernels.hip", "d8_walk.hip", "d8_fill.hip", "d8_abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -7,6 +7,15 @@
 
 #include "d8_dev.hpp"
 
+// Build-time defaults of the counts tile pass (64 x 64 tiles): waves per tile
+// of the walk kernel, or the in-LDS doubling kernel instead.
+#ifndef D8_WALK_WPT
+#define D8_WALK_WPT 1
+#endif
+#ifndef D8_COUNT_DOUBLING
+#define D8_COUNT_DOUBLING 1
+#endif
+
 namespace d8 {
 
 // Workspace layout (all offsets 256-byte aligned):
@@ -36,6 +45,8 @@ struct Plan {
   int bw = 0, bh = 0;  // workgroup block of the tile passes (whole tiles)
   int cpt = 16;        // cells per thread of the tile passes
   const float* dem = nullptr;  // fused call: codes computed from this DEM in the emit pass
+  bool doubling = D8_COUNT_DOUBLING != 0;  // counts: tile pass by in-LDS doubling instead of walks
+  int wpt = D8_WALK_WPT;                   // counts walks: waves per 64 x 64 tile (1 or 2)
   // Streamed calls: when span > 0 the tile passes run only blocks (= tiles,
   // for 64 x 64 tiles and blocks) first .. first + span - 1.
   int64_t first = 0, span = 0;
@@ -68,6 +79,8 @@ hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, 
 void count_block_dims(int ts, int waves, int& bw, int& bh);
 hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s);
 
+// Counts tile pass with unknown inflows by last-arriver walks (64 x 64 tiles).
+hipError_t launch_walk_count(const Plan& p, const uint8_t* dirs, uint32_t* out, int wpt, hipStream_t s);
 hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
                               hipStream_t s);
 hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass,

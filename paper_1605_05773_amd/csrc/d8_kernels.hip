@@ -156,46 +156,6 @@ __global__ __launch_bounds__(16 * (64 / RPT)) void k_flowdirs(const float* __res
   }
 }
 
-// ----------------------------------------------------------- tile helpers --
-
-// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs round-robin
-// (block b runs on XCD b % 8); give each XCD a contiguous run of tiles so that
-// neighbouring tiles, which share cache lines of the direction field, meet in
-// the same L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t n) {
-  const int64_t q = n >> 3, rem = n & 7;
-  const int64_t x = bid & 7, i = bid >> 3;
-  return x * q + (x < rem ? x : rem) + i;
-}
-
-struct TileGeo {
-  DemInfo dm;
-  int64_t tile, y0, x0;
-  int tw, th;
-};
-
-__device__ __forceinline__ TileGeo tile_geo(const DemTable& tab, int64_t tile, int ts) {
-  TileGeo g;
-  g.tile = tile;
-  g.dm = dem_of_tile(tab, tile);
-  const int64_t lt = tile - g.dm.tile0;
-  const int64_t ty = lt / g.dm.TX, tx = lt - ty * g.dm.TX;
-  g.y0 = ty * ts;
-  g.x0 = tx * ts;
-  g.th = (int)min((int64_t)ts, (int64_t)g.dm.H - g.y0);
-  g.tw = (int)min((int64_t)ts, (int64_t)g.dm.W - g.x0);
-  return g;
-}
-
-// Global slot id of the perimeter cell at global (gy, gx) of the DEM dm.
-__device__ __forceinline__ int64_t slot_of_cell(const DemInfo& dm, int64_t gy, int64_t gx, int ts, int cap) {
-  const int64_t nty = gy / ts, ntx = gx / ts;
-  const int64_t ntile = dm.tile0 + nty * dm.TX + ntx;
-  const int nth = (int)min((int64_t)ts, (int64_t)dm.H - nty * ts);
-  const int ntw = (int)min((int64_t)ts, (int64_t)dm.W - ntx * ts);
-  return ntile * cap + perim_slot((int)(gy - nty * ts), (int)(gx - ntx * ts), ntw, nth);
-}
-
 // Stage a BW x BH block of direction codes with a one-cell halo into LDS
 // (row stride BW + 2).  When the block's rows are 4-byte aligned (full-width
 // block, width and offset multiples of 4) the BH + 2 rows are fetched as
@@ -1717,6 +1677,8 @@ static hipError_t tile_pass(const Plan& p, const uint8_t* dirs, const float* w, 
     }
     return hipErrorInvalidValue;
   }
+  if constexpr (kCount)
+    if (p.ts == 64 && !p.dem && !p.doubling) return launch_walk_count(p, dirs, static_cast<uint32_t*>(out), p.wpt, s);
   if (p.ts == 32 && p.bw == 32 && p.bh == 32) return emit_blk<32, 32, 32, V>(p, dirs, w, out, out_lo, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 32) return emit_blk<64, 32, 32, V>(p, dirs, w, out, out_lo, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 64) return emit_blk<64, 64, 32, V>(p, dirs, w, out, out_lo, s);
