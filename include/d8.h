@@ -119,6 +119,23 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
                    d8_dtype out_dtype, void* out, float* out_lo, void* ws, size_t ws_bytes, int tile,
                    void* stream);
 
+/* For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same as d8_accum, with the
+ * workspace taken from a static device array of the library
+ * (D8_NOALLOC_SCRATCH_BYTES per GPU; each GPU the library runs on holds it
+ * until the process ends) instead of a caller workspace; the call allocates
+ * nothing.  Shapes whose d8_workspace_bytes exceed the array (at tile 64
+ * about 2.9 bytes per cell, so up to about 4800 x 4800 cells) return
+ * D8_ENOMEM and enqueue nothing.  Every call on one GPU uses that GPU's array:
+ * calls that overlap in time on one GPU (concurrent streams, threads) race.
+ * status: NULL, or a device uint32 that receives, on `stream` after the
+ * call's kernels, its data-error word (0; bit 0: a bad direction code or a
+ * target off the grid or into NoData; bit 1: a cycle). */
+#define D8_NOALLOC_SCRATCH_BYTES (64u << 20)
+d8_status d8_accum_noalloc(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights,
+                           d8_dtype out_dtype, void* out, float* out_lo, int tile, uint32_t* status,
+                           void* stream);
+
 /* Fused flow directions and counts: dem (float32, NaN = NoData) -> dirs and
  * out, equal to d8_flowdirs followed by d8_accum with unit weights and
  * D8_U32 output.  The tile pass computes each tile's codes from the DEM

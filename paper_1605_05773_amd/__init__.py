@@ -54,6 +54,7 @@ def lib():
             "d8_flowdirs_steepest": ([P, I64, I64, P, P], I32),
             "d8_workspace_bytes": ([I64, I64, I32], SZ),
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
+            "d8_accum_noalloc": ([P, I64, I64, P, I32, P, P, I32, P, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
             "d8_accum_dem": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
             "d8_accum_streamed_workspace_bytes": ([I64, I64, I64], SZ),
@@ -84,6 +85,7 @@ EXPORTED = (
     "d8_batched_workspace_bytes", "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
     "d8_fill_workspace_bytes", "d8_fill_eps", "d8_accum_streamed_workspace_bytes", "d8_accum_streamed",
+    "d8_accum_noalloc",
 )
 NPHASES = 10
 
@@ -170,6 +172,37 @@ def accum(dirs: torch.Tensor, weights: torch.Tensor | None = None, *, tile: int 
                           out.data_ptr(), None if out_lo is None else out_lo.data_ptr(), ws.data_ptr(), ws.numel(),
                           tile, _stream(dirs.device)), "d8_accum")
     _maybe_debug_check(ws, dirs.device)
+    return out
+
+
+def accum_noalloc(dirs: torch.Tensor, weights: torch.Tensor | None = None, *, out: torch.Tensor,
+                  out_lo: torch.Tensor | None = None, tile: int = 0, status: torch.Tensor | None = None) -> torch.Tensor:
+    """accum() for callers that cannot allocate: the library's static device
+    scratch replaces the workspace and nothing is allocated, so `out` (and
+    `status`, a device int32/uint32 tensor of one element that receives the
+    data-error word) must be given.  Raises D8Error(D8_ENOMEM) for shapes the
+    scratch cannot hold."""
+    dirs = _dev_tensor(dirs, torch.uint8, "dirs")
+    H, W = dirs.shape
+    if out.dtype == torch.uint32:
+        dt = D8_U32
+    else:
+        dt = D8_F32
+        _dev_tensor(out, torch.float32, "out")
+    if weights is not None:
+        weights = _dev_tensor(weights, torch.float32, "weights")
+    if out.shape != dirs.shape or (weights is not None and weights.shape != dirs.shape):
+        raise ValueError("shape mismatch")
+    if out_lo is not None:
+        _dev_tensor(out_lo, torch.float32, "out_lo")
+    st = None
+    if status is not None:
+        if not status.is_cuda or status.numel() < 1 or status.element_size() != 4:
+            raise TypeError("status: expected a device tensor of one 32-bit element")
+        st = status.data_ptr()
+    _check(lib().d8_accum_noalloc(dirs.data_ptr(), H, W, None if weights is None else weights.data_ptr(), dt,
+                                  out.data_ptr(), None if out_lo is None else out_lo.data_ptr(), tile, st,
+                                  _stream(dirs.device)), "d8_accum_noalloc")
     return out
 
 

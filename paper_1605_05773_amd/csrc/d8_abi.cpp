@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -315,6 +316,60 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
   if (st != D8_OK) return st;
   if (out_dtype == D8_F32 && p.ts > 64) return D8_EUNSUPPORTED;
   return run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- no-alloc --
+namespace d8 {
+// The workspace of d8_accum_noalloc: a static device array, one copy per GPU
+// that loads the library.  Host code must use its device address (from
+// hipGetSymbolAddress on the current device), never the symbol itself.
+static __device__ __align__(256) uint8_t scratch[D8_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::atomic<void*> g_scratch[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per
+// device), or nullptr if the lookup fails.
+static void* scratch_here() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  void* p = g_scratch[dev].load(std::memory_order_acquire);
+  if (p) return p;
+  void* q = nullptr;
+  if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return nullptr;
+  g_scratch[dev].store(q, std::memory_order_release);
+  return q;
+}
+
+__global__ void k_copy_status(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+}  // namespace d8
+
+extern "C" {
+
+d8_status d8_accum_noalloc(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights,
+                           d8_dtype out_dtype, void* out, float* out_lo, int tile, uint32_t* status,
+                           void* stream) {
+  if (!dirs || !out) return D8_EINVAL;
+  if (out_dtype != D8_U32 && out_dtype != D8_F32) return D8_EINVAL;
+  if (out_dtype == D8_U32 && (weights || out_lo)) return D8_EINVAL;
+  const size_t need = d8_workspace_bytes(rows, cols, tile);
+  if (!need) return D8_EINVAL;
+  if (need > (size_t)D8_NOALLOC_SCRATCH_BYTES) return D8_ENOMEM;
+  void* ws = scratch_here();
+  if (!ws) return D8_EHIP;
+  Plan p;
+  d8_status st = prep_single(p, rows, cols, ws, (size_t)D8_NOALLOC_SCRATCH_BYTES, tile);
+  if (st != D8_OK) return st;
+  if (out_dtype == D8_F32 && p.ts > 64) return D8_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  st = run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, s);
+  if (st != D8_OK || !status) return st;
+  hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, p.hdr, status);
+  return hip_status(hipGetLastError());
 }
 
 d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* dirs, uint32_t* out, void* ws,

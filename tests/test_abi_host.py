@@ -72,6 +72,13 @@ def test_argument_errors_before_device_work():
     assert L.d8_accum_dem(fake, 10, 10, None, fake, fake, 1 << 20, 0, None) == d8.D8_EINVAL
     assert L.d8_flowdirs_steepest(fake, 0, 10, fake, None) == d8.D8_EINVAL
     assert L.d8_device_status(None, None, None) == d8.D8_EINVAL
+    # the no-allocation variant: same argument rules, and shapes beyond its
+    # static scratch are refused before any device work
+    assert L.d8_accum_noalloc(None, 10, 10, None, d8.D8_U32, fake, None, 0, None, None) == d8.D8_EINVAL
+    assert L.d8_accum_noalloc(fake, 10, 10, fake, d8.D8_U32, fake, None, 0, None, None) == d8.D8_EINVAL
+    assert L.d8_accum_noalloc(fake, 0, 10, None, d8.D8_U32, fake, None, 0, None, None) == d8.D8_EINVAL
+    assert L.d8_accum_noalloc(fake, 8192, 8192, None, d8.D8_U32, fake, None, 0, None, None) == d8.D8_ENOMEM
+    assert L.d8_workspace_bytes(4800, 4800, 64) <= 64 << 20 < L.d8_workspace_bytes(8192, 8192, 64)
 
 
 def test_batched_workspace_validation():
