@@ -74,7 +74,8 @@ typedef struct {
   int32_t cols;
 } d8_desc;
 
-/* Tile sides accepted by `tile` (0 = library default, currently 64). */
+/* Tile sides accepted by `tile`: 0 (library default, 64), 32, 64, and 128
+ * for counts.  Larger tiles do not fit a CU's 160 KiB of LDS. */
 #define D8_TILE_DEFAULT 0
 
 /* ------------------------------------------------------------------------ */
@@ -114,7 +115,7 @@ size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile);
  * out_lo: NULL, or float32 [rows*cols] receiving RN32(sum - out), so that
  *   out + out_lo carries about 48 significant bits of the fp64 sum (weighted
  *   only).
- * ws / ws_bytes: workspace.  tile: 0, 32, 64 or 128. */
+ * ws / ws_bytes: workspace.  tile: 0, 32, 64, or 128 (counts only). */
 d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float* weights,
                    d8_dtype out_dtype, void* out, float* out_lo, void* ws, size_t ws_bytes, int tile,
                    void* stream);
@@ -205,9 +206,17 @@ d8_status d8_fill_eps(const float* dem, int64_t rows, int64_t cols, float eps, f
 /* ------------------------------------------------------------------------ */
 /* Batched: n DEMs of uneven shapes packed in one buffer, one set of launches
  * for the whole batch.  host_desc / dev_desc describe the same n DEMs (host
- * and device copies).  A DEM may not exceed 2^31-1 cells.  `waves` is the
- * number of 64-lane waves per tile workgroup (0 = default); see
- * d8_autotune_batched. */
+ * and device copies).  A DEM may not exceed 2^31-1 cells.
+ * `waves` (0 = default) picks the launch shape of the tile passes:
+ *   tile 64: one tile per workgroup of 64 * waves threads; waves 2, 4, 8
+ *     (default) or 16, i.e. 32, 16, 8 or 4 cells per thread of the in-LDS
+ *     doubling pass; for counts (D8_U32) waves 1, 2 and 4 instead select the
+ *     last-arriver walk pass (Alg. 2's queue) with that many waves per tile;
+ *   tile 32: workgroups of waves = 1 (default), 2 or 4 tiles, 64 * waves
+ *     threads, 16 cells per thread;
+ *   tile 128 (counts only): one tile per workgroup of 1024 threads (waves 16).
+ * Other values return D8_EUNSUPPORTED.  d8_autotune_batched times every
+ * shape the fp64 passes accept. */
 
 size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile);
 
@@ -227,10 +236,13 @@ d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* h
                                     float* gw_packed, void* ws, size_t ws_bytes, int tile, int waves,
                                     void* stream);
 
-/* Times the batched forward+backward for every supported (tile, waves) pair on
- * the given inputs (synchronising `stream`) and writes the fastest pair.
- * Outputs are scratch.  ws must be sized for the largest tile side tried
- * (d8_batched_workspace_bytes with tile 32). */
+/* Times the batched weighted forward+backward (d8_accum_batched with D8_F32,
+ * then d8_accum_backward_batched) at every (tile, waves) pair the fp64 passes
+ * accept -- tile 32 with waves 1, 2, 4 and tile 64 with waves 2, 4, 8, 16 --
+ * on the given inputs (synchronising `stream`), best of two timed repeats
+ * after one warm-up, and writes the fastest pair.  Outputs are scratch.  ws
+ * must be sized for the largest tile side tried (d8_batched_workspace_bytes
+ * with tile 32). */
 d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
                               int32_t n, const float* w_packed, float* out_scratch, float* g_scratch,
                               void* ws, size_t ws_bytes, int* best_tile, int* best_waves, float* best_ms,

@@ -59,18 +59,6 @@ static int pick_tile(int tile) {
   return 0;
 }
 
-// Threads per tile workgroup: at most 64 cells per thread (source bit mask),
-// at most 16 for the backward pass (register double buffer).
-static int pick_threads(int ts, int waves, bool backward) {
-  int nt = waves > 0 ? 64 * waves : (ts == 32 ? 64 : (ts == 64 ? 256 : 1024));
-  const int cells = ts * ts;
-  const int maxc = backward ? 16 : 64;
-  while (nt < 1024 && (cells + nt - 1) / nt > maxc) nt *= 2;
-  if (nt > 1024) nt = 1024;
-  if (nt > cells) nt = std::max(64, cells);
-  return nt;
-}
-
 // At most 2^32 - 1 cells (uint32 counts and cell numbering) and at most
 // 2^31 - 1 rows or columns (the kernels' DEM descriptor holds 32-bit sides).
 static bool shape_ok(int64_t rows, int64_t cols) {
@@ -97,13 +85,15 @@ static DemInfo single_dem(int64_t rows, int64_t cols, int ts, int waves = 0) {
   return d;
 }
 
-static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves) {
+// Launch shape of the tile passes for `waves` (waves_ok): cells per thread
+// of the doubling passes on 64 x 64 tiles (64 / waves), or, for counts with
+// waves 1, 2 or 4, the walk pass with that many waves per tile.
+static void set_blocks(Plan& p, const d8_desc* hd, int32_t n, int64_t rows, int64_t cols, int waves,
+                       bool counts = false) {
   count_block_dims(p.ts, waves, p.bw, p.bh);
-  // 64 x 64 tiles: waves 2 / 4 / 8 / 16 -> 32 / 16 / 8 / 4 cells per thread
-  // (default 8: 512 threads)
   p.cpt = 16;
-  if (p.bw == 64 && p.bh == 64 && p.ts == 64)
-    p.cpt = waves == 2 ? 32 : (waves == 4 ? 16 : (waves == 16 ? 4 : 8));
+  if (p.ts == 64) p.cpt = waves >= 2 ? 64 / waves : 8;
+  p.wpt = (counts && p.ts == 64 && (waves == 1 || waves == 2 || waves == 4)) ? waves : 0;
   p.nblocks = 0;
   p.nsb = 0;
   if (hd) {
@@ -247,14 +237,13 @@ static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size
 }
 
 static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w, d8_dtype out_dtype, void* out,
-                             float* out_lo, int waves, hipStream_t s) {
+                             float* out_lo, hipStream_t s) {
   hipError_t e = launch_zero_header(p.hdr, s);
   if (e != hipSuccess) return D8_EHIP;
   if (out_dtype == D8_U32) {
-    const int nt = pick_threads(p.ts, waves, false);
     {
       PhaseScope ps(kPhCountEmit, s);
-      if ((e = launch_count_tiles(p, dirs, false, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
+      if ((e = launch_count_tiles(p, dirs, false, static_cast<uint32_t*>(out), s)) != hipSuccess) return D8_EHIP;
     }
     {
       PhaseScope ps(kPhCountResolve, s);
@@ -262,14 +251,13 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
     }
     {
       PhaseScope ps(kPhCountFinal, s);
-      if ((e = launch_count_tiles(p, dirs, true, static_cast<uint32_t*>(out), nt, s)) != hipSuccess) return D8_EHIP;
+      if ((e = launch_count_tiles(p, dirs, true, static_cast<uint32_t*>(out), s)) != hipSuccess) return D8_EHIP;
     }
   } else {
     if (p.ts > 64) return D8_EUNSUPPORTED;
-    const int nt = pick_threads(p.ts, waves, false);
     {
       PhaseScope ps(kPhWEmit, s);
-      if ((e = launch_weighted_tiles(p, dirs, w, false, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
+      if ((e = launch_weighted_tiles(p, dirs, w, false, static_cast<float*>(out), out_lo, s)) != hipSuccess)
         return D8_EHIP;
     }
     {
@@ -278,22 +266,20 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
     }
     {
       PhaseScope ps(kPhWFinal, s);
-      if ((e = launch_weighted_tiles(p, dirs, w, true, static_cast<float*>(out), out_lo, nt, s)) != hipSuccess)
+      if ((e = launch_weighted_tiles(p, dirs, w, true, static_cast<float*>(out), out_lo, s)) != hipSuccess)
         return D8_EHIP;
     }
   }
   return D8_OK;
 }
 
-static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g, float* gw, int waves,
-                              hipStream_t s) {
+static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g, float* gw, hipStream_t s) {
   if (p.ts > 64) return D8_EUNSUPPORTED;
   hipError_t e = launch_zero_header(p.hdr, s);
   if (e != hipSuccess) return D8_EHIP;
-  const int nt = pick_threads(p.ts, waves, true);
   {
     PhaseScope ps(kPhBEmit, s);
-    if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, nt, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, s)) != hipSuccess) return D8_EHIP;
   }
   {
     PhaseScope ps(kPhBResolve, s);
@@ -301,7 +287,7 @@ static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g
   }
   {
     PhaseScope ps(kPhBFinal, s);
-    if ((e = launch_backward_tiles(p, dirs, g, true, gw, nt, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_backward_tiles(p, dirs, g, true, gw, s)) != hipSuccess) return D8_EHIP;
   }
   return D8_OK;
 }
@@ -315,7 +301,7 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
   d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
   if (st != D8_OK) return st;
   if (out_dtype == D8_F32 && p.ts > 64) return D8_EUNSUPPORTED;
-  return run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, (hipStream_t)stream);
+  return run_forward(p, dirs, weights, out_dtype, out, out_lo, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -366,7 +352,7 @@ d8_status d8_accum_noalloc(const uint8_t* dirs, int64_t rows, int64_t cols, cons
   if (st != D8_OK) return st;
   if (out_dtype == D8_F32 && p.ts > 64) return D8_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
-  st = run_forward(p, dirs, weights, out_dtype, out, out_lo, 0, s);
+  st = run_forward(p, dirs, weights, out_dtype, out, out_lo, s);
   if (st != D8_OK || !status) return st;
   hipLaunchKernelGGL(k_copy_status, dim3(1), dim3(64), 0, s, p.hdr, status);
   return hip_status(hipGetLastError());
@@ -379,7 +365,7 @@ d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* di
   d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
   if (st != D8_OK) return st;
   p.dem = dem;  // the emit pass computes (and writes) the codes
-  return run_forward(p, dirs, nullptr, D8_U32, out, nullptr, 0, (hipStream_t)stream);
+  return run_forward(p, dirs, nullptr, D8_U32, out, nullptr, (hipStream_t)stream);
 }
 
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
@@ -389,7 +375,7 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
   d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
   if (st != D8_OK) return st;
   if (p.ts > 64) return D8_EUNSUPPORTED;
-  return run_backward(p, dirs, grad_out, grad_weights, 0, (hipStream_t)stream);
+  return run_backward(p, dirs, grad_out, grad_weights, (hipStream_t)stream);
 }
 
 // ----------------------------------------------------------------- streamed --
@@ -497,7 +483,7 @@ d8_status d8_accum_streamed(const uint8_t* dirs_host, int64_t rows, int64_t cols
       // the strip's tile rows; buffers addressed by global cell index
       p.first = (s0 / 64) * tx;
       p.span = ((s1 - s0 + 63) / 64) * tx;
-      if (launch_count_tiles(p, dbuf[b] - r0 * cols, pass == 1, obuf[b] - s0 * cols, 0, s) != hipSuccess ||
+      if (launch_count_tiles(p, dbuf[b] - r0 * cols, pass == 1, obuf[b] - s0 * cols, s) != hipSuccess ||
           hipEventRecord(ss.done[b], s) != hipSuccess || hipStreamWaitEvent(ss.out, ss.done[b], 0) != hipSuccess ||
           hipMemcpyAsync(out_host + s0 * cols, obuf[b], (size_t)(s1 - s0) * (size_t)cols * 4, hipMemcpyDeviceToHost,
                          ss.out) != hipSuccess ||
@@ -599,13 +585,13 @@ size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile)
 }
 
 static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int32_t n, void* ws, size_t ws_bytes,
-                              int ts, hipStream_t s, int waves = 0) {
+                              int ts, hipStream_t s, int waves = 0, bool counts = false) {
   int64_t nt;
   if (!ts || !dd || !ws || !batch_tiles(hd, n, ts, nt)) return D8_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
   if (plan_layout(p, nt, ts, n, nullptr) > ws_bytes) return D8_ENOMEM;
   plan_layout(p, nt, ts, n, ws);
-  set_blocks(p, hd, n, 0, 0, waves);
+  set_blocks(p, hd, n, 0, 0, waves, counts);
   if (n == 1) {
     p.tab.n = 1;
     p.tab.dev = nullptr;
@@ -658,12 +644,14 @@ d8_status d8_accum_batched(const uint8_t* dirs_packed, const d8_desc* host_desc,
   if (out_dtype == D8_U32 && (w_packed || out_lo_packed)) return D8_EINVAL;
   if (waves < 0 || waves > 16) return D8_EINVAL;
   const int ts = pick_tile(tile);
+  if (!ts) return D8_EINVAL;
   if (out_dtype == D8_F32 && ts > 64) return D8_EUNSUPPORTED;
+  if (!waves_ok(ts, waves, out_dtype == D8_U32)) return D8_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan p;
-  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves);
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves, out_dtype == D8_U32);
   if (st != D8_OK) return st;
-  return run_forward(p, dirs_packed, w_packed, out_dtype, out_packed, out_lo_packed, waves, s);
+  return run_forward(p, dirs_packed, w_packed, out_dtype, out_packed, out_lo_packed, s);
 }
 
 d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
@@ -672,12 +660,13 @@ d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* h
   if (!dirs_packed || !g_packed || !gw_packed) return D8_EINVAL;
   if (waves < 0 || waves > 16) return D8_EINVAL;
   const int ts = pick_tile(tile);
-  if (ts > 64) return D8_EUNSUPPORTED;
+  if (!ts) return D8_EINVAL;
+  if (ts > 64 || !waves_ok(ts, waves, false)) return D8_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan p;
-  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s);
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves);
   if (st != D8_OK) return st;
-  return run_backward(p, dirs_packed, g_packed, gw_packed, waves, s);
+  return run_backward(p, dirs_packed, g_packed, gw_packed, s);
 }
 
 d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
@@ -691,15 +680,18 @@ d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_de
     (void)hipEventDestroy(e0);
     return D8_EHIP;
   }
+  // every (tile, waves) launch shape of the fp64 tile passes: tile 32 with 1,
+  // 2 or 4 tiles per workgroup, tile 64 with 2..16 waves per tile (fp64
+  // tiles of 128 or 256 cells do not fit the 160 KiB of LDS of a CU)
   const int tiles[2] = {32, 64};
-  const int waves_opts[4] = {1, 2, 4, 8};
+  const int waves_opts[5] = {1, 2, 4, 8, 16};
   float best = 1e30f;
   int bt = 0, bw = 0;
   d8_status last = D8_OK;
   for (int ti = 0; ti < 2; ++ti) {
-    for (int wi = 0; wi < 4; ++wi) {
+    for (int wi = 0; wi < 5; ++wi) {
       const int t = tiles[ti], w = waves_opts[wi];
-      if (64 * w > t * t) continue;
+      if (!waves_ok(t, w, false)) continue;
       float ms_best = 1e30f;
       bool ok = true;
       for (int rep = 0; rep < 3 && ok; ++rep) {

@@ -7,15 +7,6 @@
 
 #include "d8_dev.hpp"
 
-// Build-time defaults of the counts tile pass (64 x 64 tiles): waves per tile
-// of the walk kernel, or the in-LDS doubling kernel instead.
-#ifndef D8_WALK_WPT
-#define D8_WALK_WPT 1
-#endif
-#ifndef D8_COUNT_DOUBLING
-#define D8_COUNT_DOUBLING 1
-#endif
-
 namespace d8 {
 
 // Workspace layout (all offsets 256-byte aligned):
@@ -45,8 +36,7 @@ struct Plan {
   int bw = 0, bh = 0;  // workgroup block of the tile passes (whole tiles)
   int cpt = 16;        // cells per thread of the tile passes
   const float* dem = nullptr;  // fused call: codes computed from this DEM in the emit pass
-  bool doubling = D8_COUNT_DOUBLING != 0;  // counts: tile pass by in-LDS doubling instead of walks
-  int wpt = D8_WALK_WPT;                   // counts walks: waves per 64 x 64 tile (1 or 2)
+  int wpt = 0;        // counts, 64 x 64 tiles: waves per tile of the walk pass (0: the doubling pass)
   // Streamed calls: when span > 0 the tile passes run only blocks (= tiles,
   // for 64 x 64 tiles and blocks) first .. first + span - 1.
   int64_t first = 0, span = 0;
@@ -76,17 +66,20 @@ hipError_t launch_flowdirs(const float* dem, uint8_t* dirs, const DemTable& tab,
                            bool steepest = false);
 hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, int bh, DemInfo* out,
                                hipStream_t s);
+// Workgroup shape of the tile passes for a tile side and `waves` (waves_ok).
 void count_block_dims(int ts, int waves, int& bw, int& bh);
+// Whether `waves` (0 = default) names a tile-pass launch shape for tile side
+// ts; counts additionally accept the walk pass (tile 64, waves 1, 2, 4).
+bool waves_ok(int ts, int waves, bool counts);
 hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s);
 
 // Counts tile pass with unknown inflows by last-arriver walks (64 x 64 tiles).
 hipError_t launch_walk_count(const Plan& p, const uint8_t* dirs, uint32_t* out, int wpt, hipStream_t s);
-hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
-                              hipStream_t s);
+hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, hipStream_t s);
 hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass,
-                                 float* out, float* out_lo, int nt, hipStream_t s);
+                                 float* out, float* out_lo, hipStream_t s);
 hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float* g, bool final_pass,
-                                 float* out, int nt, hipStream_t s);
+                                 float* out, hipStream_t s);
 hipError_t launch_forward_resolve(const Plan& p, bool weighted, hipStream_t s);
 hipError_t launch_backward_resolve(const Plan& p, hipStream_t s);
 

@@ -692,9 +692,12 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
       for (int q = 0; q < KG; ++q) {
         const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
         cw[q] = D[(r * W + c4) / 4];
-        o4[q] = *reinterpret_cast<const OV4*>(O + r * W + c4);
-        if constexpr (!kCount)
+        // counts: the tile-local values are read after the walks, only for
+        // groups a walk touched
+        if constexpr (!kCount) {
+          o4[q] = *reinterpret_cast<const OV4*>(O + r * W + c4);
           l4[q] = L ? *reinterpret_cast<const float4*>(L + r * W + c4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
       }
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
@@ -712,16 +715,32 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
       fixup_walks<TS, V, NRX>(code, Y, hr, xr, g.th, g.tw);
       __syncthreads();
       D8_STAMP(1, 2);
+      if constexpr (kCount) {
+        // touched groups: read the 4 tile-local values (loads issued for all
+        // groups first), add, write the group back whole
+        uint4 y[KG];
+        bool tq[KG];
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
+          y[q] = reinterpret_cast<const uint4*>(Y)[j];
+          tq[q] = (y[q].x | y[q].y | y[q].z | y[q].w) != 0u;
+          if (tq[q]) o4[q] = *reinterpret_cast<const OV4*>(O + r * W + c4);
+        }
+#pragma unroll
+        for (int q = 0; q < KG; ++q) {
+          const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
+          if (tq[q])
+            *reinterpret_cast<OV4*>(O + r * W + c4) =
+                make_uint4(o4[q].x + y[q].x, o4[q].y + y[q].y, o4[q].z + y[q].z, o4[q].w + y[q].w);
+        }
+      }
 #pragma unroll
       for (int q = 0; q < KG; ++q) {
         const int j = tid + q * NT, r = j / GPR, c4 = (j % GPR) * 4;
         const int64_t e = r * W + c4;
         if constexpr (kCount) {
-          const uint4 y = reinterpret_cast<const uint4*>(Y)[j];
-          if (y.x) O[e + 0] = o4[q].x + y.x;
-          if (y.y) O[e + 1] = o4[q].y + y.y;
-          if (y.z) O[e + 2] = o4[q].z + y.z;
-          if (y.w) O[e + 3] = o4[q].w + y.w;
+          (void)e;
         } else {
           const double2 ya = reinterpret_cast<const double2*>(Y)[2 * j];
           const double2 yb = reinterpret_cast<const double2*>(Y)[2 * j + 1];
@@ -1562,29 +1581,53 @@ __global__ void k_clear_flags(uint32_t* hdr) {
   if (i < 128) hdr[64 + i] = 0;
 }
 
-// Builds the per-DEM table of a batch from the caller's device descriptors
-// (a serial prefix over the DEMs; n is small).
-__global__ void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int ts, int bw, int bh, DemInfo* out) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  int64_t t0 = 0, b0 = 0, s0 = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    DemInfo d;
-    d.off = desc[i].offset;
-    d.H = desc[i].rows;
-    d.W = desc[i].cols;
-    d.TY = (d.H + ts - 1) / ts;
-    d.TX = (d.W + ts - 1) / ts;
-    d.tile0 = t0;
-    d.BY = (d.H + bh - 1) / bh;
-    d.BX = (d.W + bw - 1) / bw;
-    d.blk0 = b0;
-    d.SBY = (d.H + kSuper - 1) / kSuper;
-    d.SBX = (d.W + kSuper - 1) / kSuper;
-    d.sb0 = s0;
-    t0 += (int64_t)d.TY * d.TX;
-    b0 += (int64_t)d.BY * d.BX;
-    s0 += (int64_t)d.SBY * d.SBX;
-    out[i] = d;
+// Builds the per-DEM table of a batch from the caller's device descriptors:
+// one workgroup, the DEMs in chunks of 1024 with an LDS scan of the tile,
+// block and super-block counts per chunk (first tile id etc. of each DEM).
+__global__ __launch_bounds__(1024) void k_build_demtab(const d8_desc* __restrict__ desc, int32_t n, int ts, int bw,
+                                                      int bh, DemInfo* out) {
+  __shared__ int64_t sc[3][1024];
+  __shared__ int64_t carry[3];
+  const int tid = threadIdx.x;
+  if (tid < 3) carry[tid] = 0;
+  __syncthreads();
+  for (int32_t c0 = 0; c0 < n; c0 += 1024) {
+    const int32_t i = c0 + tid;
+    DemInfo d{};
+    int64_t cnt[3] = {0, 0, 0};
+    if (i < n) {
+      d.off = desc[i].offset;
+      d.H = desc[i].rows;
+      d.W = desc[i].cols;
+      d.TY = (d.H + ts - 1) / ts;
+      d.TX = (d.W + ts - 1) / ts;
+      d.BY = (d.H + bh - 1) / bh;
+      d.BX = (d.W + bw - 1) / bw;
+      d.SBY = (d.H + kSuper - 1) / kSuper;
+      d.SBX = (d.W + kSuper - 1) / kSuper;
+      cnt[0] = (int64_t)d.TY * d.TX;
+      cnt[1] = (int64_t)d.BY * d.BX;
+      cnt[2] = (int64_t)d.SBY * d.SBX;
+    }
+    for (int k = 0; k < 3; ++k) sc[k][tid] = cnt[k];
+    __syncthreads();
+    // inclusive scan (Hillis-Steele) over the chunk
+    for (int dlt = 1; dlt < 1024; dlt <<= 1) {
+      int64_t v[3];
+      for (int k = 0; k < 3; ++k) v[k] = tid >= dlt ? sc[k][tid - dlt] : 0;
+      __syncthreads();
+      for (int k = 0; k < 3; ++k) sc[k][tid] += v[k];
+      __syncthreads();
+    }
+    if (i < n) {
+      d.tile0 = carry[0] + sc[0][tid] - cnt[0];
+      d.blk0 = carry[1] + sc[1][tid] - cnt[1];
+      d.sb0 = carry[2] + sc[2][tid] - cnt[2];
+      out[i] = d;
+    }
+    __syncthreads();
+    if (tid < 3) carry[tid] += sc[tid][1023];
+    __syncthreads();
   }
 }
 
@@ -1604,8 +1647,8 @@ hipError_t launch_zero_header(uint32_t* hdr, hipStream_t s) {
 
 hipError_t launch_build_demtab(const void* desc_dev, int32_t n, int ts, int bw, int bh, DemInfo* out,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_build_demtab, dim3(1), dim3(64), 0, s, reinterpret_cast<const d8_desc*>(desc_dev), n, ts, bw,
-                     bh, out);
+  hipLaunchKernelGGL(k_build_demtab, dim3(1), dim3(1024), 0, s, reinterpret_cast<const d8_desc*>(desc_dev), n, ts,
+                     bw, bh, out);
   return hipGetLastError();
 }
 
@@ -1652,8 +1695,11 @@ static hipError_t fixup_ts(const Plan& p, const uint8_t* dirs, void* out, float*
   return hipGetLastError();
 }
 
-// Block shape of the emit pass for a tile side and wave count (whole tiles
-// per block, 16 cells per thread).
+// Launch shape of the tile passes.  Tile 64: one 64 x 64 tile per workgroup
+// of 64 * waves threads, waves 2, 4, 8 (default) or 16, i.e. 32, 16, 8 or 4
+// cells per thread (counts also take the walk pass, waves 1, 2, 4).  Tile 32:
+// workgroups of waves = 1 (default), 2 or 4 tiles, 16 cells per thread.
+// Tile 128 (counts): one tile per workgroup of 1024 threads (waves 16).
 void count_block_dims(int ts, int waves, int& bw, int& bh) {
   if (ts == 32) {
     bw = waves >= 2 ? 64 : 32;
@@ -1662,6 +1708,14 @@ void count_block_dims(int ts, int waves, int& bw, int& bh) {
     bw = ts;
     bh = ts;
   }
+}
+
+bool waves_ok(int ts, int waves, bool counts) {
+  if (waves == 0) return true;
+  if (ts == 32) return waves == 1 || waves == 2 || waves == 4;
+  if (ts == 64) return waves == 2 || waves == 4 || waves == 8 || waves == 16 || (counts && waves == 1);
+  if (ts == 128) return counts && waves == 16;
+  return false;
 }
 
 template <typename V>
@@ -1678,7 +1732,7 @@ static hipError_t tile_pass(const Plan& p, const uint8_t* dirs, const float* w, 
     return hipErrorInvalidValue;
   }
   if constexpr (kCount)
-    if (p.ts == 64 && !p.dem && !p.doubling) return launch_walk_count(p, dirs, static_cast<uint32_t*>(out), p.wpt, s);
+    if (p.ts == 64 && !p.dem && p.wpt > 0) return launch_walk_count(p, dirs, static_cast<uint32_t*>(out), p.wpt, s);
   if (p.ts == 32 && p.bw == 32 && p.bh == 32) return emit_blk<32, 32, 32, V>(p, dirs, w, out, out_lo, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 32) return emit_blk<64, 32, 32, V>(p, dirs, w, out, out_lo, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 64) return emit_blk<64, 64, 32, V>(p, dirs, w, out, out_lo, s);
@@ -1688,15 +1742,12 @@ static hipError_t tile_pass(const Plan& p, const uint8_t* dirs, const float* w, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, int nt,
-                              hipStream_t s) {
-  (void)nt;
+hipError_t launch_count_tiles(const Plan& p, const uint8_t* dirs, bool final_pass, uint32_t* out, hipStream_t s) {
   return tile_pass<uint32_t>(p, dirs, nullptr, final_pass, out, nullptr, s);
 }
 
 hipError_t launch_weighted_tiles(const Plan& p, const uint8_t* dirs, const float* w, bool final_pass, float* out,
-                                 float* out_lo, int nt, hipStream_t s) {
-  (void)nt;
+                                 float* out_lo, hipStream_t s) {
   return tile_pass<double>(p, dirs, w, final_pass, out, out_lo, s);
 }
 
@@ -1726,8 +1777,7 @@ static hipError_t bwd_blk(const Plan& p, const uint8_t* dirs, const float* g, bo
 }
 
 hipError_t launch_backward_tiles(const Plan& p, const uint8_t* dirs, const float* g, bool final_pass, float* out,
-                                 int nt, hipStream_t s) {
-  (void)nt;
+                                 hipStream_t s) {
   if (p.ts == 32 && p.bw == 32 && p.bh == 32) return bwd_blk<32, 32, 32>(p, dirs, g, final_pass, out, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 32) return bwd_blk<64, 32, 32>(p, dirs, g, final_pass, out, s);
   if (p.ts == 32 && p.bw == 64 && p.bh == 64) return bwd_blk<64, 64, 32>(p, dirs, g, final_pass, out, s);

@@ -74,6 +74,15 @@ __device__ __forceinline__ uint32_t high_bytes(uint32_t w) {
   return (((w & 0x7F7F7F7Fu) + 0x77777777u) | w) & 0x80808080u;
 }
 
+// Workgroup barrier that orders LDS only: it waits for this wave's LDS
+// operations, not for its global stores (a full __syncthreads would wait for
+// the previous tile's output stores to reach memory).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -90,7 +99,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* sc, uint32_
     if (lane >= d) v += y;
   }
   if (lane == 63) sc[wv] = v;
-  __syncthreads();
+  lds_barrier();
   uint32_t before = 0, tot = 0;
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) {
@@ -98,7 +107,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* sc, uint32_
     before += w < wv ? s : 0u;
     tot += s;
   }
-  __syncthreads();
+  lds_barrier();
   total = tot;
   return before + v - x;
 }
@@ -201,9 +210,9 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
     return band0 + k < band1 ? band0 + (int64_t)k : (int64_t)-1;
   };
   if (tid < 8) cnt[tid] = tid == 0 ? (uint32_t)grab() : 0u;
-  __syncthreads();
+  lds_barrier();
   int64_t cur = (int32_t)cnt[0];
-  __syncthreads();  // every thread has read cnt[0] before it is reused
+  lds_barrier();  // every thread has read cnt[0] before it is reused
   TileCodes<RPT> tc;
   TileGeo g{};
   if (cur >= 0) {
@@ -235,7 +244,7 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
     for (int k = 0; k < RPT; ++k)
       anyhi |= high_bytes(tc.c[k].x) | high_bytes(tc.c[k].y) | high_bytes(tc.c[k].z) | high_bytes(tc.c[k].w);
     if (anyhi) cnt[7] = 1u;
-    __syncthreads();
+    lds_barrier();
     const int64_t nxt = (int32_t)cnt[0];
     const bool slow = cnt[7] != 0u;
     uint32_t s4[RPT][4];
@@ -285,7 +294,7 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
         *reinterpret_cast<uint4*>(&wd[widx(r, c0 + 4 * qq)]) = v;
       }
     }
-    __syncthreads();
+    lds_barrier();
     WSTAMP(2);
     // ---- pending inputs: every cell that drains somewhere adds one to its
     // target's count (cells draining out of the tile count into the border).
@@ -422,7 +431,7 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       WSTAMP(4);
       const bool last_phase = ph == nphase - 1;
 
@@ -507,7 +516,7 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
           act = cont;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
     WSTAMP(6);
 
@@ -576,7 +585,7 @@ __global__ __launch_bounds__(64 * WPT) __attribute__((amdgpu_waves_per_eu(WalkOc
     }
 #endif
     if (tid > 0 && tid < 8) cnt[tid] = 0u;
-    __syncthreads();  // LDS reused by the next tile
+    lds_barrier();  // LDS reused by the next tile
     cur = nxt;
     g = gn;
     tc = tn;

@@ -62,7 +62,8 @@ def test_autotune_and_cache(small_batch, tmp_path):
     wp = b.pack([to_dev(demgen.lognormal_f32(s, 10 + i)) for i, s in enumerate(shapes)], torch.float32)
     cache = tmp_path / "tune.json"
     t, w, ms = d8.autotune_batched(b, dp, wp, cache_path=str(cache))
-    assert t in (32, 64) and w in (1, 2, 4, 8) and ms > 0
+    assert (t == 32 and w in (1, 2, 4)) or (t == 64 and w in (2, 4, 8, 16))
+    assert ms > 0
     stored = json.loads(cache.read_text())
     assert list(stored.values()) == [{"tile": t, "waves": w, "ms": ms}]
     assert d8.autotune_batched(b, dp, wp, cache_path=str(cache)) == (t, w, ms)

@@ -345,7 +345,11 @@ def test_batched_matches_single(tile, waves):
 
 # ------------------------------------------- every tile / waves configuration
 
-CONFIGS = [(32, 1), (32, 2), (32, 4), (64, 1), (64, 2), (64, 4), (64, 8), (64, 16), (128, 8), (128, 16)]
+# every launch shape of the counts tile passes: tile 32 with 1, 2, 4 tiles
+# per workgroup; tile 64 walk pass with 1, 2, 4 waves and doubling pass with
+# 8, 16 waves (and the defaults); tile 128
+CONFIGS = [(32, 0), (32, 1), (32, 2), (32, 4), (64, 0), (64, 1), (64, 2), (64, 4), (64, 8), (64, 16), (128, 0),
+           (128, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -366,7 +370,7 @@ def test_counts_every_config_2k(dem2k, tile, waves):
     np.testing.assert_array_equal(got, ref)
 
 
-@pytest.mark.parametrize("tile,waves", [(32, 1), (32, 2), (64, 4), (64, 8)])
+@pytest.mark.parametrize("tile,waves", [(32, 1), (32, 2), (32, 4), (64, 2), (64, 4), (64, 8), (64, 16)])
 def test_weighted_and_backward_every_config_2k(dem2k, tile, waves):
     d, _ = dem2k
     H, W = d.shape
@@ -377,6 +381,21 @@ def test_weighted_and_backward_every_config_2k(dem2k, tile, waves):
     assert_rel(to_np(A).reshape(H, W), oracle.accum_f64(d, w), 1e-6, "weighted")
     G = d8.accum_backward_batched(b, dd, to_dev(w).reshape(-1), tile=tile, waves=waves)
     assert_rel(to_np(G).reshape(H, W), oracle.backward_f64(d, w), 1e-6, "backward")
+
+
+def test_unsupported_launch_shapes_are_refused(dem2k):
+    d, _ = dem2k
+    H, W = d.shape
+    b = d8.Batch([(H, W)], dev())
+    dd = to_dev(d).reshape(-1)
+    w = torch.ones(H * W, dtype=torch.float32, device=dev())
+    for tile, waves, weighted in [(32, 8, False), (32, 16, False), (64, 1, True), (128, 8, False), (64, 3, False)]:
+        with pytest.raises(d8.D8Error) as e:
+            d8.accum_batched(b, dd, w if weighted else None, tile=tile, waves=waves)
+        assert e.value.status == d8.D8_EUNSUPPORTED, (tile, waves, weighted)
+    with pytest.raises(d8.D8Error) as e:
+        d8.accum_backward_batched(b, dd, w, tile=64, waves=1)
+    assert e.value.status == d8.D8_EUNSUPPORTED
 
 
 # ------------------------------------------------ host-resident (streamed)
