@@ -131,10 +131,12 @@ __device__ __forceinline__ TileGeo tile_geo(const DemTable& tab, int64_t tile, i
   TileGeo g;
   g.tile = tile;
   g.dm = dem_of_tile(tab, tile);
-  const int64_t lt = tile - g.dm.tile0;
-  const int64_t ty = lt / g.dm.TX, tx = lt - ty * g.dm.TX;
-  g.y0 = ty * ts;
-  g.x0 = tx * ts;
+  // tile index within its DEM: below 2^32 (a DEM has fewer than 2^32 cells),
+  // so a 32-bit division
+  const uint32_t lt = (uint32_t)(tile - g.dm.tile0);
+  const uint32_t ty = lt / (uint32_t)g.dm.TX, tx = lt - ty * (uint32_t)g.dm.TX;
+  g.y0 = (int64_t)ty * ts;
+  g.x0 = (int64_t)tx * ts;
   g.th = (int)min((int64_t)ts, (int64_t)g.dm.H - g.y0);
   g.tw = (int)min((int64_t)ts, (int64_t)g.dm.W - g.x0);
   return g;

@@ -83,8 +83,8 @@ __global__ __launch_bounds__(16 * (64 / RPT)) void k_flowdirs(const float* __res
                                                              uint8_t* __restrict__ dirs, DemTable tab) {
   const int64_t tile = blockIdx.x;
   const DemInfo dm = dem_of_tile(tab, tile);
-  const int64_t lt = tile - dm.tile0;
-  const int64_t ty = lt / dm.TX, tx = lt - ty * dm.TX;
+  const uint32_t lt = (uint32_t)(tile - dm.tile0);  // below 2^32: a 32-bit division
+  const int64_t ty = lt / (uint32_t)dm.TX, tx = lt - (uint32_t)ty * (uint32_t)dm.TX;
   const int64_t H = dm.H, W = dm.W;
   const float* z = dem + dm.off;
   uint8_t* d = dirs + dm.off;
@@ -393,12 +393,13 @@ template <int BW, int BH, int TS>
 __device__ __forceinline__ BlockGeo block_geo(const DemTable& tab, int64_t blk) {
   BlockGeo b;
   b.dm = dem_of_block(tab, blk);
-  const int64_t lb = blk - b.dm.blk0;
-  const int64_t by = lb / b.dm.BX, bx = lb - by * b.dm.BX;
-  b.y0 = by * BH;
-  b.x0 = bx * BW;
-  b.ty0 = by * (BH / TS);
-  b.tx0 = bx * (BW / TS);
+  // block index within its DEM: below 2^32 (a DEM has fewer than 2^32 cells)
+  const uint32_t lb = (uint32_t)(blk - b.dm.blk0);
+  const uint32_t by = lb / (uint32_t)b.dm.BX, bx = lb - by * (uint32_t)b.dm.BX;
+  b.y0 = (int64_t)by * BH;
+  b.x0 = (int64_t)bx * BW;
+  b.ty0 = (int64_t)by * (BH / TS);
+  b.tx0 = (int64_t)bx * (BW / TS);
   b.bh = (int)min((int64_t)BH, (int64_t)b.dm.H - b.y0);
   b.bw = (int)min((int64_t)BW, (int64_t)b.dm.W - b.x0);
   return b;
@@ -613,24 +614,31 @@ __device__ __forceinline__ int hoff(uint32_t d) {
 // sums are exact for counts and fp64 for weights), then the touched cells of
 // the output are updated.
 // Walks of the finalising pass: each receiver q with inflow xr[q] adds it at
-// every cell of its in-tile path (row stride TS), atomically into Y.
+// every cell of its in-tile path (row stride TS), atomically into Y.  The
+// walk loop runs while any lane of the wave is still walking (a uniform
+// test), and a lane's own stop conditions are folded into one flag rather than
+// taken as separate branches, so that the loop does little exec-mask work.
 template <int TS, typename V, int NRX>
 __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int (&hr)[NRX], const V (&xr)[NRX],
                                             int th, int tw) {
   constexpr int NC = TS * TS;
 #pragma unroll
   for (int q = 0; q < NRX; ++q) {
-    if (hr[q] < 0 || xr[q] == (V)0) continue;
     const V x = xr[q];
-    int r = hr[q] / TS, c = hr[q] % TS;
-    for (int n = 0; n < NC; ++n) {  // bounded: a cycle never ends
-      const uint32_t k = code[r * TS + c];
-      if (k >= kOutside) break;  // a NoData target (flagged by the emit pass)
-      atomicAdd(&Y[r * TS + c], x);
-      if (k >= 8u) break;        // outlet (or an invalid code, flagged by the emit pass)
-      r += ddr_t(k);
-      c += ddc_t(k);
-      if (r < 0 || r >= th || c < 0 || c >= tw) break;  // left the tile
+    bool live = hr[q] >= 0 && x != (V)0;
+    int r = live ? hr[q] / TS : 0, c = live ? hr[q] % TS : 0;
+    // bounded: a cycle never ends
+    for (int n = 0; n < NC && __builtin_amdgcn_ballot_w64(live); ++n) {
+      const int p = r * TS + c;
+      const uint32_t k = code[p];
+      const bool add = live & (k < kOutside);  // not a NoData target (flagged by the emit pass)
+      if (add) atomicAdd(&Y[p], x);
+      // stop at an outlet (or an invalid code, flagged by the emit pass) or
+      // where the path leaves the tile
+      const int nr = r + ddr_t(k & 7u), nc = c + ddc_t(k & 7u);
+      live = add & (k < 8u) & ((unsigned)nr < (unsigned)th) & ((unsigned)nc < (unsigned)tw);
+      r = live ? nr : r;
+      c = live ? nc : c;
     }
   }
 }
@@ -1068,8 +1076,8 @@ __global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const 
   D8_STAMP(DOWN ? 3 : 2, 0);
   const int64_t sbid = xcd_tile(blockIdx.x, nsb);
   const DemInfo dm = dem_of_sb(tab, sbid);
-  const int64_t lsb = sbid - dm.sb0;
-  const int64_t sby = lsb / dm.SBX, sbx = lsb - sby * dm.SBX;
+  const uint32_t lsb = (uint32_t)(sbid - dm.sb0);  // below 2^32: a 32-bit division
+  const int64_t sby = lsb / (uint32_t)dm.SBX, sbx = lsb - (uint32_t)sby * (uint32_t)dm.SBX;
   const int64_t ty0 = sby * G, tx0 = sbx * G;
   const int64_t y0 = sby * kSuper, x0 = sbx * kSuper;
   const int sbh = (int)min((int64_t)kSuper, (int64_t)dm.H - y0);
@@ -1810,24 +1818,26 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   V* b2 = reinterpret_cast<V*>(p.buf[2]);
   // Nodes: at most one per super-block perimeter cell.  One thread per node
-  // for the single passes (their work is a chain of dependent random
-  // accesses); the rounds loop over the nodes with a capped grid.
+  // for the walks (their work is a chain of dependent random accesses); the
+  // other passes loop over the nodes with a grid of one resident wave of
+  // workgroups (2048 x 256 threads fill the GPU), so a round with nothing
+  // left to do costs one small dispatch.
   const int64_t maxn = std::min<int64_t>(p.nslots, p.nsb * 4 * kSuper);
   const unsigned gn = (unsigned)std::max<int64_t>(1, (maxn + 255) / 256);
-  const unsigned g = (unsigned)std::min<int64_t>(gn, 16384);
+  const unsigned g = (unsigned)std::min<int64_t>(gn, 2048);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
   group_pass<LV, V, false>(p, s);
   uint64_t* pend = p.buf[2];
-  hipLaunchKernelGGL((k_l2_init<V>), dim3(gn), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
   // Counts only: the weighted stage 1 would need a fence between its two
   // atomics (an L2 write-back on this GPU) per step; doubling does it all.
   if constexpr (std::is_same<V, uint64_t>::value)
     hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
-  hipLaunchKernelGGL((k_l2_prep<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
+  hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
   for (int j = 0; j < p.rounds; ++j)
     hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, p.hdr);
   hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
-  hipLaunchKernelGGL((k_l2_fold<V>), dim3(gn), dim3(256), 0, s, b0, b1, b2, p.hdr);
+  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, p.hdr);
   group_pass<LV, V, true>(p, s);
   return hipGetLastError();
 }
