@@ -1046,7 +1046,9 @@ struct GroupDims {
   static constexpr int G = kSuper / TS;
   static constexpr int CAP = 4 * TS - 4;
   static constexpr int NN = G * G * CAP;
-  static constexpr int NT = 512;
+  // threads: few nodes per thread keep the per-node registers (and with them
+  // the waves a CU can hold) in check: 1024 x 4 nodes for 64 x 64 tiles
+  static constexpr int NT = TS <= 64 ? 1024 : 512;
   static constexpr int NPT = (NN + NT - 1) / NT;
 };
 
@@ -1060,7 +1062,7 @@ __device__ __forceinline__ void ladd(double* p, double v) { atomicAdd(p, v); }
 // reaches (-1: it ends inside the super-block).  The down pass reads the
 // resolved node values from F (indexed through sbroot).
 template <int TS, typename LV, typename V, bool DOWN>
-__global__ __launch_bounds__(512) void k_group(DemTable tab, int64_t nsb, const uint8_t* __restrict__ ex_code,
+__global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, int64_t nsb, const uint8_t* __restrict__ ex_code,
                                                const uint16_t* __restrict__ rl, V* __restrict__ ex_val,
                                                V* __restrict__ l2val, int32_t* __restrict__ sbroot,
                                                int32_t* __restrict__ l2par, V* __restrict__ l2acc,
@@ -1799,7 +1801,8 @@ static void group_launch(const Plan& p, hipStream_t s) {
   V* b0 = reinterpret_cast<V*>(p.buf[0]);
   V* b1 = reinterpret_cast<V*>(p.buf[1]);
   uint64_t* b2 = p.buf[2];
-  hipLaunchKernelGGL((k_group<TS, LV, V, DOWN>), dim3((unsigned)p.nsb), dim3(512), 0, s, p.tab, p.nsb, p.ex_code,
+  hipLaunchKernelGGL((k_group<TS, LV, V, DOWN>), dim3((unsigned)p.nsb), dim3(GroupDims<TS, LV>::NT), 0, s, p.tab,
+                     p.nsb, p.ex_code,
                      p.rl, ev, b0, p.anc[1], p.anc[0], b1, b2, b0, reinterpret_cast<V*>(b2), p.hdr, p.hdr);
 }
 
