@@ -613,32 +613,46 @@ __device__ __forceinline__ int hoff(uint32_t d) {
 // walks its path accumulating into an LDS array (paths may share cells; the
 // sums are exact for counts and fp64 for weights), then the touched cells of
 // the output are updated.
+// Before the walks, every perimeter cell whose step leaves the tile gets the
+// outlet code in the tile's LDS copy of the codes, so that a walk stops there
+// after adding and never needs its coordinates: it moves by the in-tile offset
+// of the code alone.
+template <int TS, int NRX>
+__device__ __forceinline__ void mark_tile_exits(uint8_t* code, const int (&hr)[NRX], int th, int tw) {
+#pragma unroll
+  for (int q = 0; q < NRX; ++q) {
+    if (hr[q] < 0) continue;
+    const uint32_t k = code[hr[q]];
+    if (k < 8u) {
+      const int nr = hr[q] / TS + ddr_t(k), nc = hr[q] % TS + ddc_t(k);
+      if ((unsigned)nr >= (unsigned)th || (unsigned)nc >= (unsigned)tw) code[hr[q]] = kNone;
+    }
+  }
+}
+
 // Walks of the finalising pass: each receiver q with inflow xr[q] adds it at
 // every cell of its in-tile path (row stride TS), atomically into Y.  The
 // walk loop runs while any lane of the wave is still walking (a uniform
-// test), and a lane's own stop conditions are folded into one flag rather than
+// test), and a lane's stop conditions are folded into one flag rather than
 // taken as separate branches, so that the loop does little exec-mask work.
 template <int TS, typename V, int NRX>
-__device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int (&hr)[NRX], const V (&xr)[NRX],
-                                            int th, int tw) {
+__device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int (&hr)[NRX], const V (&xr)[NRX]) {
   constexpr int NC = TS * TS;
 #pragma unroll
   for (int q = 0; q < NRX; ++q) {
     const V x = xr[q];
     bool live = hr[q] >= 0 && x != (V)0;
-    int r = live ? hr[q] / TS : 0, c = live ? hr[q] % TS : 0;
+    int p = live ? hr[q] : 0;
     // bounded: a cycle never ends
     for (int n = 0; n < NC && __builtin_amdgcn_ballot_w64(live); ++n) {
-      const int p = r * TS + c;
       const uint32_t k = code[p];
       const bool add = live & (k < kOutside);  // not a NoData target (flagged by the emit pass)
       if (add) atomicAdd(&Y[p], x);
-      // stop at an outlet (or an invalid code, flagged by the emit pass) or
-      // where the path leaves the tile
-      const int nr = r + ddr_t(k & 7u), nc = c + ddc_t(k & 7u);
-      live = add & (k < 8u) & ((unsigned)nr < (unsigned)th) & ((unsigned)nc < (unsigned)tw);
-      r = live ? nr : r;
-      c = live ? nc : c;
+      // on to the next cell unless this one is an outlet, an exit of the tile
+      // (marked as an outlet) or carries an invalid code (flagged by the emit
+      // pass)
+      live = add & (k < 8u);
+      p = live ? p + hoff<TS>(k) : p;
     }
   }
 }
@@ -719,8 +733,10 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
         }
       }
       __syncthreads();
+      mark_tile_exits<TS, NRX>(code, hr, g.th, g.tw);
+      __syncthreads();
       D8_STAMP(1, 1);
-      fixup_walks<TS, V, NRX>(code, Y, hr, xr, g.th, g.tw);
+      fixup_walks<TS, V, NRX>(code, Y, hr, xr);
       __syncthreads();
       D8_STAMP(1, 2);
       if constexpr (kCount) {
@@ -794,9 +810,11 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
     Y[tid + k * NT] = 0;
   }
   __syncthreads();
+  mark_tile_exits<TS, NRX>(code, hr, g.th, g.tw);
+  __syncthreads();
   D8_STAMP(1, 1);
   // Walks: add the inflow at every cell of the receiver's in-tile path.
-  fixup_walks<TS, V, NRX>(code, Y, hr, xr, g.th, g.tw);
+  fixup_walks<TS, V, NRX>(code, Y, hr, xr);
   __syncthreads();
   D8_STAMP(1, 2);
   // The tile-local values written by the emit pass were fetched at the start
