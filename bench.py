@@ -306,7 +306,7 @@ def main():
         w3 = torch.from_numpy(demgen.lognormal_f32(zc3.shape, 303)).to(dev)
         g3 = torch.from_numpy(demgen.lognormal_f32(zc3.shape, 304)).to(dev)
         o3 = torch.empty(zc3.shape, dtype=torch.float32, device=dev)
-        ws3 = torch.empty(d8.workspace_bytes(*zc3.shape, 0) + 256, dtype=torch.uint8, device=dev)
+        ws3 = torch.empty(d8.workspace_bytes(*zc3.shape, 0, backward=True) + 256, dtype=torch.uint8, device=dev)
         ws3 = ws3[(-ws3.data_ptr()) % 256:]
         for _ in range(2):
             d8.accum(d3, w3, out=o3, ws=ws3)

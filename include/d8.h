@@ -102,9 +102,15 @@ d8_status d8_flowdirs_steepest(const float* dem, int64_t rows, int64_t cols, uin
 /* ------------------------------------------------------------------------ */
 /* Up-slope area (Eq. 1) over a direction field. */
 
-/* Bytes of workspace d8_accum / d8_accum_backward need for this shape and tile
- * (0 = default).  Returns 0 for an invalid shape or tile. */
+/* Bytes of workspace the forward calls (d8_accum, d8_accum_dem) need for this
+ * shape and tile (0 = default).  Returns 0 for an invalid shape or tile. */
 size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile);
+
+/* Bytes of workspace d8_accum_backward needs: d8_workspace_bytes plus 6 bytes
+ * per cell, which hold between its two tile passes each cell's in-tile path
+ * sum (low part) and the tile exit its path leaves by.  Returns 0 for an
+ * invalid shape or tile. */
+size_t d8_backward_workspace_bytes(int64_t rows, int64_t cols, int tile);
 
 /* dirs: uint8 codes [rows*cols].
  * weights: float32 [rows*cols], or NULL for unit weights.
@@ -151,7 +157,11 @@ d8_status d8_accum_dem(const float* dem, int64_t rows, int64_t cols, uint8_t* di
  * A = (I - P)^-1 w with P the D8 drainage matrix, so for a loss with
  * dL/dA = grad_out the gradient is grad_weights = (I - P)^-T grad_out:
  * grad_weights(c) = sum of grad_out over the cells on c's downstream path,
- * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0. */
+ * c included.  grad_out, grad_weights: float32 [rows*cols]; NoData -> 0.
+ * Path sums in fp64 (the in-tile part carried between the tile passes as a
+ * float32 pair, to 2^-48 of its magnitude), rounded to float32 once, in a
+ * fixed order: the result is the same on every run.  ws_bytes: at least
+ * d8_backward_workspace_bytes(rows, cols, tile).  tile: 0, 32 or 64. */
 d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, const float* grad_out,
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream);
 
@@ -218,7 +228,10 @@ d8_status d8_fill_eps(const float* dem, int64_t rows, int64_t cols, float eps, f
  * Other values return D8_EUNSUPPORTED.  d8_autotune_batched times every
  * shape the fp64 passes accept. */
 
+/* Workspace of the batched forward calls, and of d8_accum_backward_batched
+ * (6 more bytes per packed cell, up to the largest offset + rows * cols). */
 size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile);
+size_t d8_batched_backward_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile);
 
 /* Flow directions for every DEM of the batch (same rule as d8_flowdirs).
  * ws: workspace of d8_batched_workspace_bytes(host_desc, n, 0) bytes (only
@@ -241,8 +254,8 @@ d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* h
  * accept -- tile 32 with waves 1, 2, 4 and tile 64 with waves 2, 4, 8, 16 --
  * on the given inputs (synchronising `stream`), best of two timed repeats
  * after one warm-up, and writes the fastest pair.  Outputs are scratch.  ws
- * must be sized for the largest tile side tried (d8_batched_workspace_bytes
- * with tile 32). */
+ * must be sized for the backward at the largest tile side tried
+ * (d8_batched_backward_workspace_bytes with tile 32). */
 d8_status d8_autotune_batched(const uint8_t* dirs_packed, const d8_desc* host_desc, const d8_desc* dev_desc,
                               int32_t n, const float* w_packed, float* out_scratch, float* g_scratch,
                               void* ws, size_t ws_bytes, int* best_tile, int* best_waves, float* best_ms,

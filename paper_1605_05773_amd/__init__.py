@@ -53,6 +53,7 @@ def lib():
             "d8_flowdirs": ([P, I64, I64, P, P], I32),
             "d8_flowdirs_steepest": ([P, I64, I64, P, P], I32),
             "d8_workspace_bytes": ([I64, I64, I32], SZ),
+            "d8_backward_workspace_bytes": ([I64, I64, I32], SZ),
             "d8_accum": ([P, I64, I64, P, I32, P, P, P, SZ, I32, P], I32),
             "d8_accum_noalloc": ([P, I64, I64, P, I32, P, P, I32, P, P], I32),
             "d8_accum_backward": ([P, I64, I64, P, P, P, SZ, I32, P], I32),
@@ -62,6 +63,7 @@ def lib():
             "d8_fill_workspace_bytes": ([I64, I64], SZ),
             "d8_fill_eps": ([P, I64, I64, ctypes.c_float, P, P, SZ, P, P], I32),
             "d8_batched_workspace_bytes": ([P, I32, I32], SZ),
+            "d8_batched_backward_workspace_bytes": ([P, I32, I32], SZ),
             "d8_flowdirs_batched": ([P, P, P, I32, P, P, SZ, P], I32),
             "d8_accum_batched": ([P, P, P, I32, P, I32, P, P, P, SZ, I32, I32, P], I32),
             "d8_accum_backward_batched": ([P, P, P, I32, P, P, P, SZ, I32, I32, P], I32),
@@ -85,7 +87,7 @@ EXPORTED = (
     "d8_batched_workspace_bytes", "d8_flowdirs_batched", "d8_accum_batched", "d8_accum_backward_batched", "d8_autotune_batched",
     "d8_device_status", "d8_strerror", "d8_version", "d8_phase_timing", "d8_phase_report",
     "d8_fill_workspace_bytes", "d8_fill_eps", "d8_accum_streamed_workspace_bytes", "d8_accum_streamed",
-    "d8_accum_noalloc",
+    "d8_accum_noalloc", "d8_backward_workspace_bytes", "d8_batched_backward_workspace_bytes",
 )
 NPHASES = 10
 
@@ -139,10 +141,12 @@ def flowdirs(dem: torch.Tensor, rule: str = "lowest") -> torch.Tensor:
     return out
 
 
-def workspace_bytes(rows: int, cols: int, tile: int = 0) -> int:
-    n = lib().d8_workspace_bytes(rows, cols, tile)
+def workspace_bytes(rows: int, cols: int, tile: int = 0, backward: bool = False) -> int:
+    """Workspace bytes of the forward calls, or of the backward (backward=True)."""
+    f = lib().d8_backward_workspace_bytes if backward else lib().d8_workspace_bytes
+    n = f(rows, cols, tile)
     if n == 0:
-        raise D8Error(D8_EINVAL, "d8_workspace_bytes")
+        raise D8Error(D8_EINVAL, "d8_backward_workspace_bytes" if backward else "d8_workspace_bytes")
     return n
 
 
@@ -278,7 +282,7 @@ def accum_backward(dirs: torch.Tensor, grad_out: torch.Tensor, *, tile: int = 0,
     grad_out = _dev_tensor(grad_out, torch.float32, "grad_out")
     H, W = dirs.shape
     gw = torch.empty((H, W), dtype=torch.float32, device=dirs.device)
-    nb = workspace_bytes(H, W, tile)
+    nb = workspace_bytes(H, W, tile, backward=True)
     if ws is None:
         ws = workspace(nb, dirs.device)
     _check(lib().d8_accum_backward(dirs.data_ptr(), H, W, grad_out.data_ptr(), gw.data_ptr(), ws.data_ptr(),
@@ -373,8 +377,10 @@ class Batch:
     def unpack(self, packed):
         return [packed[off:off + r * c].view(r, c) for off, (r, c) in zip(self.offsets, self.shapes)]
 
-    def workspace_bytes(self, tile=0):
-        n = lib().d8_batched_workspace_bytes(ctypes.addressof(self.host_desc), self.n, tile)
+    def workspace_bytes(self, tile=0, backward=False):
+        """Workspace bytes of the batched forward calls, or of the backward."""
+        f = lib().d8_batched_backward_workspace_bytes if backward else lib().d8_batched_workspace_bytes
+        n = f(ctypes.addressof(self.host_desc), self.n, tile)
         if n == 0:
             raise D8Error(D8_EINVAL, "d8_batched_workspace_bytes")
         return n
@@ -413,7 +419,7 @@ def accum_backward_batched(batch: Batch, dirs_packed, g_packed, *, tile=0, waves
     dirs_packed = _dev_tensor(dirs_packed, torch.uint8, "dirs_packed")
     g_packed = _dev_tensor(g_packed, torch.float32, "g_packed")
     out = torch.empty(batch.total, dtype=torch.float32, device=batch.device) if out is None else out
-    nb = batch.workspace_bytes(tile)
+    nb = batch.workspace_bytes(tile, backward=True)
     ws = workspace(nb, batch.device) if ws is None else ws
     _check(lib().d8_accum_backward_batched(dirs_packed.data_ptr(), ctypes.addressof(batch.host_desc),
                                            batch.dev_desc.data_ptr(), batch.n, g_packed.data_ptr(), out.data_ptr(),
@@ -451,7 +457,7 @@ def autotune_batched(batch: Batch, dirs_packed, w_packed, *, cache_path=None):
     w_packed = _dev_tensor(w_packed, torch.float32, "w_packed")
     out = torch.empty(batch.total, dtype=torch.float32, device=batch.device)
     g = torch.empty(batch.total, dtype=torch.float32, device=batch.device)
-    ws = workspace(batch.workspace_bytes(32), batch.device)
+    ws = workspace(batch.workspace_bytes(32, backward=True), batch.device)
     bt, bw, ms = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_float(0)
     _check(lib().d8_autotune_batched(dirs_packed.data_ptr(), ctypes.addressof(batch.host_desc),
                                      batch.dev_desc.data_ptr(), batch.n, w_packed.data_ptr(), out.data_ptr(),
@@ -488,7 +494,7 @@ class BatchedGraph:
         self.g = torch.zeros(n, dtype=torch.float32, device=dev)
         self.area = torch.zeros(n, dtype=torch.float32, device=dev)
         self.grad = torch.zeros(n, dtype=torch.float32, device=dev)
-        nb = batch.workspace_bytes(tile)
+        nb = batch.workspace_bytes(tile, backward=True)  # serves the forward too
         raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
         pad = (-raw.data_ptr()) % 256
         self._raw = raw

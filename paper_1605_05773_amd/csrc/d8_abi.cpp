@@ -15,7 +15,7 @@ namespace d8 {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, void* base) {
   p.ts = ts;
   p.cap = 4 * ts - 4;
   p.ntiles = ntiles;
@@ -38,6 +38,8 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
   for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
   for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
   const size_t o_list = take((size_t)p.nslots * 4);
+  const size_t o_blo = ncells > 0 ? take((size_t)ncells * 4) : 0;
+  const size_t o_broot = ncells > 0 ? take((size_t)ncells * 2) : 0;
   p.bytes = off;
   if (base) {
     char* b = static_cast<char*>(base);
@@ -49,6 +51,8 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base) {
     for (int i = 0; i < 3; ++i) p.buf[i] = reinterpret_cast<uint64_t*>(b + o_buf[i]);
     for (int i = 0; i < 2; ++i) p.anc[i] = reinterpret_cast<int32_t*>(b + o_anc[i]);
     p.list = reinterpret_cast<int32_t*>(b + o_list);
+    p.blo = ncells > 0 ? reinterpret_cast<float*>(b + o_blo) : nullptr;
+    p.broot = ncells > 0 ? reinterpret_cast<uint16_t*>(b + o_broot) : nullptr;
   }
   return p.bytes;
 }
@@ -219,16 +223,27 @@ size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile) {
   if (!ts || !shape_ok(rows, cols)) return 0;
   Plan p;
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
-  return plan_layout(p, nt, ts, 1, nullptr);
+  return plan_layout(p, nt, ts, 1, 0, nullptr);
 }
 
-static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size_t ws_bytes, int tile) {
+size_t d8_backward_workspace_bytes(int64_t rows, int64_t cols, int tile) {
+  const int ts = pick_tile(tile);
+  if (!ts || !shape_ok(rows, cols)) return 0;
+  Plan p;
+  const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
+  return plan_layout(p, nt, ts, 1, rows * cols, nullptr);
+}
+
+// backward: the workspace also holds the per-cell exit array.
+static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size_t ws_bytes, int tile,
+                             bool backward = false) {
   const int ts = pick_tile(tile);
   if (!ts || !shape_ok(rows, cols) || !ws) return D8_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
-  if (plan_layout(p, nt, ts, 1, nullptr) > ws_bytes) return D8_ENOMEM;
-  plan_layout(p, nt, ts, 1, ws);
+  const int64_t nc = backward ? rows * cols : 0;
+  if (plan_layout(p, nt, ts, 1, nc, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, 1, nc, ws);
   set_blocks(p, nullptr, 1, rows, cols, 0);
   p.tab.n = 1;
   p.tab.dev = nullptr;
@@ -275,11 +290,12 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
 
 static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g, float* gw, hipStream_t s) {
   if (p.ts > 64) return D8_EUNSUPPORTED;
+  if (!p.broot || !p.blo) return D8_EINVAL;
   hipError_t e = launch_zero_header(p.hdr, s);
   if (e != hipSuccess) return D8_EHIP;
   {
     PhaseScope ps(kPhBEmit, s);
-    if ((e = launch_backward_tiles(p, dirs, g, false, nullptr, s)) != hipSuccess) return D8_EHIP;
+    if ((e = launch_backward_tiles(p, dirs, g, false, gw, s)) != hipSuccess) return D8_EHIP;
   }
   {
     PhaseScope ps(kPhBResolve, s);
@@ -372,7 +388,7 @@ d8_status d8_accum_backward(const uint8_t* dirs, int64_t rows, int64_t cols, con
                             float* grad_weights, void* ws, size_t ws_bytes, int tile, void* stream) {
   if (!dirs || !grad_out || !grad_weights) return D8_EINVAL;
   Plan p;
-  d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile);
+  d8_status st = prep_single(p, rows, cols, ws, ws_bytes, tile, true);
   if (st != D8_OK) return st;
   if (p.ts > 64) return D8_EUNSUPPORTED;
   return run_backward(p, dirs, grad_out, grad_weights, (hipStream_t)stream);
@@ -573,6 +589,13 @@ static bool batch_tiles(const d8_desc* hd, int32_t n, int ts, int64_t& ntiles) {
   return true;
 }
 
+// Extent of the packed cells: the largest offset + rows * cols.
+static int64_t batch_span(const d8_desc* hd, int32_t n) {
+  int64_t e = 0;
+  for (int32_t i = 0; i < n; ++i) e = std::max<int64_t>(e, hd[i].offset + (int64_t)hd[i].rows * hd[i].cols);
+  return e;
+}
+
 size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile) {
   const int ts = pick_tile(tile);
   int64_t nt;
@@ -580,17 +603,26 @@ size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile)
   int64_t ntf;
   batch_tiles(host_desc, n, kFlowdirsBlock, ntf);
   Plan p;
-  size_t b = plan_layout(p, nt, ts, n, nullptr);
+  size_t b = plan_layout(p, nt, ts, n, 0, nullptr);
   return std::max(b, align256(kHdrBytes) + align256(sizeof(DemInfo) * (size_t)n));
 }
 
+size_t d8_batched_backward_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile) {
+  const int ts = pick_tile(tile);
+  int64_t nt;
+  if (!ts || !batch_tiles(host_desc, n, ts, nt)) return 0;
+  Plan p;
+  return plan_layout(p, nt, ts, n, batch_span(host_desc, n), nullptr);
+}
+
 static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int32_t n, void* ws, size_t ws_bytes,
-                              int ts, hipStream_t s, int waves = 0, bool counts = false) {
+                              int ts, hipStream_t s, int waves = 0, bool counts = false, bool backward = false) {
   int64_t nt;
   if (!ts || !dd || !ws || !batch_tiles(hd, n, ts, nt)) return D8_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
-  if (plan_layout(p, nt, ts, n, nullptr) > ws_bytes) return D8_ENOMEM;
-  plan_layout(p, nt, ts, n, ws);
+  const int64_t nc = backward ? batch_span(hd, n) : 0;
+  if (plan_layout(p, nt, ts, n, nc, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, n, nc, ws);
   set_blocks(p, hd, n, 0, 0, waves, counts);
   if (n == 1) {
     p.tab.n = 1;
@@ -664,7 +696,7 @@ d8_status d8_accum_backward_batched(const uint8_t* dirs_packed, const d8_desc* h
   if (ts > 64 || !waves_ok(ts, waves, false)) return D8_EUNSUPPORTED;
   hipStream_t s = (hipStream_t)stream;
   Plan p;
-  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves);
+  d8_status st = prep_batched(p, host_desc, dev_desc, n, ws, ws_bytes, ts, s, waves, false, true);
   if (st != D8_OK) return st;
   return run_backward(p, dirs_packed, g_packed, gw_packed, s);
 }

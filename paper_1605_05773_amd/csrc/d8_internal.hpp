@@ -25,6 +25,13 @@ namespace d8 {
 //                              nodes' ancestors by node id, anc[1] every tile
 //                              exit's super-block root node id)
 //   list     int32  x nslots   forward: second ancestor buffer of the nodes
+//   blo      float  x ncells   backward: per cell, the low part of its fp64
+//                              in-tile path sum (the high part is held in the
+//                              output between the two tile passes)
+//   broot    uint16 x ncells   backward: per cell, the perimeter index of the
+//                              exit its in-tile path leaves by (0xFFFF: none);
+//                              both by packed cell index (absent when ncells
+//                              = 0, the forward calls' layout)
 // A slot is one perimeter cell of one tile: slot id = tile * cap + perimeter
 // index (see perim_slot).
 struct Plan {
@@ -51,13 +58,16 @@ struct Plan {
   uint64_t* ex_val = nullptr;
   uint64_t* buf[3] = {nullptr, nullptr, nullptr};
   int32_t* anc[2] = {nullptr, nullptr};
+  float* blo = nullptr;
+  uint16_t* broot = nullptr;
   size_t bytes = 0;
 };
 
 constexpr size_t kHdrBytes = 4096;
 constexpr int kMaxRounds = 62;
 
-size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, void* base);
+// ncells: packed cells the backward's per-cell exit array covers (0: none).
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, void* base);
 
 // Launchers (return hipError_t of the last launch).
 // Flow directions over 64x64-cell blocks (tab built with tile side 64).

@@ -857,9 +857,14 @@ __global__ __launch_bounds__(256) void k_fixup(const uint8_t* __restrict__ dirs,
 // a fixed order, so the result is deterministic.  Block and link layout as in
 // k_block_emit (the saturating root field ends at the tile root).
 //   emit pass   writes, for every receiver, its path sum (rg) and the exit it
-//               leaves by (rl), and marks exits in ex_code;
-//   final pass  recomputes the path sums and adds H(root exit), the resolved
-//               path sum beyond the tile (0 for a path ending at an outlet).
+//               leaves by (rl), and marks exits in ex_code; for every cell,
+//               its in-tile path sum as a float32 pair (high part into the
+//               output, low part into blo: the pair keeps the fp64 sum to
+//               2^-48 of its magnitude) and the perimeter index of the exit
+//               its path leaves by (broot);
+//   final pass  adds H(root exit), the resolved path sum beyond the tile, to
+//               every cell whose path leaves the tile (a streaming pass: the
+//               in-tile sums are not recomputed).
 template <int BW, int BH>
 struct BwdSmem {
   double S[BW * BH];
@@ -867,12 +872,11 @@ struct BwdSmem {
   uint8_t code[(BW + 2) * (BH + 2)];
 };
 
-template <int BW, int BH, int TS, bool FINAL, int CPT>
+template <int BW, int BH, int TS, int CPT>
 __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
     const uint8_t* __restrict__ dirs, const float* __restrict__ gin, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, double* __restrict__ rg,
-    const double* __restrict__ H0, const double* __restrict__ H1, const uint32_t* __restrict__ hdr,
-    float* __restrict__ out, uint32_t* __restrict__ status) {
+    float* __restrict__ blo, uint16_t* __restrict__ broot, float* __restrict__ out, uint32_t* __restrict__ status) {
   constexpr int NC = BW * BH;
   constexpr int NT = NC / CPT;
   constexpr int HS = BW + 2;
@@ -980,22 +984,24 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
     return true;
   };
 
-  if (FINAL) {
-    const double* Hb = hdr[2] == 0 ? H0 : H1;
+  // Per cell: the in-tile path sum and the exit its path leaves by.
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      const int c = tid + k * NT;
-      const int r = c / BW, col = c % BW;
-      if (r < g.bh && col < g.bw) {
-        double x = s[k];
-        if (sm.code[(r + 1) * HS + col + 1] != kNoData) {
-          int64_t sl;
-          if (exit_slot((int)(sm.link[c] >> 16), sl)) x += Hb[sl];
-        }
-        out[base + r * W + col] = (float)x;
-      }
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * NT;
+    const int r = c / BW, col = c % BW;
+    if (r < g.bh && col < g.bw) {
+      const int64_t o = base + r * W + col;
+      uint16_t e = 0xFFFF;
+      int64_t sl;
+      if (sm.code[(r + 1) * HS + col + 1] != kNoData && exit_slot((int)(sm.link[c] >> 16), sl))
+        e = (uint16_t)(sl - (g.dm.tile0 + (g.ty0 + r / TS) * g.dm.TX + g.tx0 + col / TS) * cap);
+      const float hi = (float)s[k];
+      out[o] = hi;
+      blo[o] = (float)(s[k] - (double)hi);
+      broot[o] = e;
     }
-  } else {
+  }
+  {
     for (int idx = tid; idx < TPX * TPY * cap; idx += NT) {
       const int tl = idx / cap, j = idx - tl * cap;
       const int ta = tl / TPX, tb = tl - ta * TPX;
@@ -1022,6 +1028,39 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
       }
       ex_code[sb + j] = ec;
     }
+  }
+}
+
+// Final pass of the backward: G(c) = (in-tile path sum: the float32 pair in
+// the output and blo) + H(exit c's path leaves by), for the cells whose path
+// leaves the tile; fp64 additions, rounded to float32.  The other cells
+// already hold their result.
+template <int BW, int BH, int TS>
+__global__ __launch_bounds__(256) void k_bwd_final(DemTable tab, int64_t nblocks, int cap,
+                                                   const float* __restrict__ blo, const uint16_t* __restrict__ broot,
+                                                   const double* __restrict__ H0, const double* __restrict__ H1,
+                                                   const uint32_t* __restrict__ hdr, float* __restrict__ out) {
+  constexpr int NT = 256, CPT = BW * BH / NT;
+  const BlockGeo g = block_geo<BW, BH, TS>(tab, xcd_tile(blockIdx.x, nblocks));
+  const double* Hb = hdr[2] == 0 ? H0 : H1;
+  const int64_t W = g.dm.W;
+  const int64_t base = g.dm.off + g.y0 * W + g.x0;
+  // all loads of a thread first, then the dependent ones
+  uint16_t e[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = threadIdx.x + k * NT;
+    const int r = c / BW, col = c % BW;
+    e[k] = (r < g.bh && col < g.bw) ? broot[base + r * W + col] : (uint16_t)0xFFFF;
+  }
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (e[k] == 0xFFFF) continue;
+    const int c = threadIdx.x + k * NT;
+    const int r = c / BW, col = c % BW;
+    const int64_t o = base + r * W + col;
+    const int64_t sl = (g.dm.tile0 + (g.ty0 + r / TS) * g.dm.TX + g.tx0 + col / TS) * cap + e[k];
+    out[o] = (float)((double)out[o] + (double)blo[o] + Hb[sl]);
   }
 }
 
@@ -1786,11 +1825,11 @@ static hipError_t bwd_cpt(const Plan& p, const uint8_t* dirs, const float* g, bo
   const double* b1 = reinterpret_cast<const double*>(p.buf[1]);
   double* ev = reinterpret_cast<double*>(p.ex_val);
   if (fin)
-    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, true, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g,
-                       p.tab, p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_bwd_final<BW, BH, TS>), dim3((unsigned)p.nblocks), dim3(256), 0, s, p.tab, p.nblocks, p.cap,
+                       p.blo, p.broot, b0, b1, p.hdr, out);
   else
-    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, false, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g,
-                       p.tab, p.nblocks, p.cap, p.ex_code, p.rl, ev, b0, b1, p.hdr, out, p.hdr);
+    hipLaunchKernelGGL((k_block_bwd<BW, BH, TS, CPT>), dim3((unsigned)p.nblocks), dim3(NT), 0, s, dirs, g, p.tab,
+                       p.nblocks, p.cap, p.ex_code, p.rl, ev, p.blo, p.broot, out, p.hdr);
   return hipGetLastError();
 }
 

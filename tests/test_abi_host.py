@@ -48,6 +48,10 @@ def test_workspace_bytes_validation():
     b = L.d8_workspace_bytes(1000, 1000, 32)
     assert 0 < a < b                                               # smaller tiles, more perimeter slots
     assert L.d8_workspace_bytes(1, 1, 32) > 0
+    # the backward: the forward's workspace plus 6 bytes per cell
+    assert L.d8_backward_workspace_bytes(1000, 1000, 64) >= L.d8_workspace_bytes(1000, 1000, 64) + 6 * 1000 * 1000
+    assert L.d8_backward_workspace_bytes(0, 10, 0) == 0
+    assert L.d8_backward_workspace_bytes(10, 10, 48) == 0
 
 
 def test_argument_errors_before_device_work():
@@ -85,6 +89,9 @@ def test_batched_workspace_validation():
     L = d8.lib()
     descs = (d8.d8_desc * 2)(d8.d8_desc(0, 10, 20), d8.d8_desc(200, 30, 5))
     assert L.d8_batched_workspace_bytes(ctypes.addressof(descs), 2, 64) > 0
+    # backward: 6 bytes per packed cell up to the largest offset + rows * cols (200 + 150)
+    assert (L.d8_batched_backward_workspace_bytes(ctypes.addressof(descs), 2, 64)
+            >= L.d8_batched_workspace_bytes(ctypes.addressof(descs), 2, 64) + 6 * 350)
     bad = (d8.d8_desc * 1)(d8.d8_desc(0, 0, 20))
     assert L.d8_batched_workspace_bytes(ctypes.addressof(bad), 1, 64) == 0
     assert L.d8_batched_workspace_bytes(ctypes.addressof(descs), 0, 64) == 0

@@ -201,6 +201,41 @@ def test_weighted_linearity():
     assert_rel(b, oracle.accum_f64(d, (w1 + w2).astype(np.float32)), 1e-6, "linearity")
 
 
+@pytest.mark.parametrize("tile", [32, 64])
+def test_weighted_run_to_run_variation_bounded(tile):
+    """Weighted sums are fp64 with atomic additions, so their order (and the
+    last bits of the sum) can change from run to run.  Every order of adding
+    n nonnegative terms is within (n-1)u of the exact sum (u = 2^-53), and a
+    (out, out_lo) pair carries an fp64 value to 2^-48 relative (the tile-local
+    value passes through one such pair before the inflow is added), so a run
+    is within (n-1)u + 2^-47 of the exact sum and two runs, or a run and the
+    fp64 oracle, differ by at most twice that, relative, at a cell with n
+    upstream cells; float32 `out` itself may differ by one ulp only where the
+    fp64 sum sits that close to a float32 rounding boundary."""
+    d = oracle.flowdirs(demgen.fbm_dem(1024, 1000, sigma=8.0, seed=5))
+    w = demgen.lognormal_f32(d.shape, 17)
+    n = oracle.accum_u32(d).astype(np.float64)
+    ref = oracle.accum_f64(d, w)
+    bound = 2.0 * (np.maximum(n - 1.0, 0.0) * 2.0 ** -53 * 1.01 + 2.0 ** -47) * ref
+    runs = []
+    for _ in range(4):
+        hi, lo = gpu_weighted(d, w, tile, with_lo=True)
+        runs.append((hi, hi.astype(np.float64) + lo.astype(np.float64)))
+    for hi, pair in runs:
+        assert np.all(np.abs(pair - ref) <= bound), "a run leaves the fp64 bound of the exact sum"
+    for hi, pair in runs[1:]:
+        diff = np.abs(pair - runs[0][1])
+        assert np.all(diff <= bound), f"run-to-run difference {diff.max():.3e} beyond the bound"
+        # float32 outputs: equal, except that two runs whose fp64 sums straddle
+        # a float32 rounding boundary give adjacent floats, the boundary (their
+        # midpoint) then lying within the bound of either sum
+        ne = hi != runs[0][0]
+        if ne.any():
+            a, b = hi[ne].astype(np.float64), runs[0][0][ne].astype(np.float64)
+            assert np.all(np.nextafter(hi[ne], runs[0][0][ne]) == runs[0][0][ne]), "not adjacent floats"
+            assert np.all(np.abs(pair[ne] - (a + b) / 2) <= bound[ne])
+
+
 # ----------------------------------------------------------------- backward
 
 @pytest.mark.parametrize("tile", [32, 64])
@@ -293,7 +328,7 @@ def test_device_errors(weighted):
 def test_backward_device_errors():
     d = np.full((70, 70), 8, np.uint8)
     d[31, 40], d[32, 40] = 6, 2
-    ws = d8.workspace(d8.workspace_bytes(70, 70, 32), dev())
+    ws = d8.workspace(d8.workspace_bytes(70, 70, 32, backward=True), dev())
     d8.accum_backward(to_dev(d), to_dev(np.ones((70, 70), np.float32)), tile=32, ws=ws)
     assert d8.device_status(ws) == d8.D8_ECYCLE
 
