@@ -873,7 +873,7 @@ struct BwdSmem {
 };
 
 template <int BW, int BH, int TS, int CPT>
-__global__ __launch_bounds__(BW * BH / CPT) void k_block_bwd(
+__global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(CPT == 8 ? 6 : 1))) void k_block_bwd(
     const uint8_t* __restrict__ dirs, const float* __restrict__ gin, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, double* __restrict__ rg,
     float* __restrict__ blo, uint16_t* __restrict__ broot, float* __restrict__ out, uint32_t* __restrict__ status) {
