@@ -38,6 +38,7 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, vo
   for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
   for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
   const size_t o_list = take((size_t)p.nslots * 4);
+  const size_t o_plist = take((size_t)p.nslots * 4);
   const size_t o_blo = ncells > 0 ? take((size_t)ncells * 4) : 0;
   const size_t o_broot = ncells > 0 ? take((size_t)ncells * 2) : 0;
   p.bytes = off;
@@ -51,6 +52,7 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, vo
     for (int i = 0; i < 3; ++i) p.buf[i] = reinterpret_cast<uint64_t*>(b + o_buf[i]);
     for (int i = 0; i < 2; ++i) p.anc[i] = reinterpret_cast<int32_t*>(b + o_anc[i]);
     p.list = reinterpret_cast<int32_t*>(b + o_list);
+    p.plist = reinterpret_cast<int32_t*>(b + o_plist);
     p.blo = ncells > 0 ? reinterpret_cast<float*>(b + o_blo) : nullptr;
     p.broot = ncells > 0 ? reinterpret_cast<uint16_t*>(b + o_broot) : nullptr;
   }

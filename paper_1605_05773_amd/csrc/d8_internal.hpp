@@ -12,7 +12,7 @@ namespace d8 {
 // Workspace layout (all offsets 256-byte aligned):
 //   header   4096 B: [0] status word, [1] final-buffer index of the forward
 //            resolve, [2] of the backward resolve, [3] super-block exit
-//            nodes, [64..127] round flags
+//            nodes, [4] nodes in plist, [64..127] round flags
 //   demtab   DemInfo x ndem                (batched calls only)
 //   ex_code  uint8  x nslots   direction code of an exit slot, 0xFF otherwise
 //   rl       uint16 x nslots   receiver slot -> exit slot of its in-tile path
@@ -25,6 +25,8 @@ namespace d8 {
 //                              nodes' ancestors by node id, anc[1] every tile
 //                              exit's super-block root node id)
 //   list     int32  x nslots   forward: second ancestor buffer of the nodes
+//   plist    int32  x nslots   forward: the nodes taking part in the
+//                              doubling stage of the global resolve
 //   blo      float  x ncells   backward: per cell, the low part of its fp64
 //                              in-tile path sum (the high part is held in the
 //                              output between the two tile passes)
@@ -50,6 +52,7 @@ struct Plan {
   int64_t nblocks = 0;
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes
+  int32_t* plist = nullptr;  // nodes of the doubling stage of the global resolve
   DemTable tab{};
   uint32_t* hdr = nullptr;
   DemInfo* demtab = nullptr;

@@ -1504,57 +1504,77 @@ __global__ void k_l2_walk(int32_t* par, V* val, V* acc, uint64_t* pend, const ui
   }
 }
 
+// Appends node i to the list when `take` (one atomic per wave).
+__device__ __forceinline__ void append_node(int32_t* list, uint32_t* count, int32_t i, bool take) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+  if (m == 0) return;
+  const int lane = (int)__lane_id();
+  const int leader = __builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(count, (uint32_t)__builtin_popcountll(m));
+  base = __shfl(base, leader);
+  if (take) list[base + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1))] = i;
+}
+
 // Stage-2 start: ancestor = parent for unfinished and parked nodes (-1 for
 // nodes finished and delivered), unfinished nodes fold in what they received,
-// pending increments zeroed (they reuse the stage-1 words).
+// pending increments zeroed (they reuse the stage-1 words).  Counts: the
+// nodes that take part (parked and unfinished ones: a set closed under
+// ancestors, so no other node ever receives an increment) are listed in
+// plist (count hdr[4]) and the rounds and the final fold run over that list
+// only; weighted values (no stage 1: every node takes part) pass no list.
 template <typename V>
-__global__ void k_l2_prep(int32_t* anc, V* val, V* d0, V* d1, const uint64_t* pend, uint32_t* hdr) {
+__global__ void k_l2_prep(int32_t* anc, V* val, V* d0, V* d1, const uint64_t* pend, int32_t* plist, uint32_t* hdr) {
   const int64_t n = hdr[3];
   bool more = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t pa = anc[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // every lane of a wave runs the same iterations (the ballot of append_node
+  // sees whole waves)
+  for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x; i0 < n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
     int32_t a = -1;
-    if constexpr (!std::is_same<V, uint64_t>::value) {
-      a = pa;  // weighted: no stage 1 ran, every node takes part
-    } else if (pa <= -2) {
-      a = -pa - 2;
-    } else {
-      bool unfinished;
-      V part;
-      if constexpr (std::is_same<V, uint64_t>::value) {
-        const uint64_t w = d0[i];
-        unfinished = (w >> kL2Shift) != 0;
-        part = w & kL2Mask;
+    bool part = false;
+    if (i < n) {
+      const int32_t pa = anc[i];
+      if constexpr (!std::is_same<V, uint64_t>::value) {
+        a = pa;  // weighted: no stage 1 ran, every node takes part
+        part = true;
+      } else if (pa <= -2) {
+        a = -pa - 2;
+        part = true;
       } else {
-        unfinished = (*reinterpret_cast<const uint32_t*>(&pend[i]) & ~kL2HasKids) != 0;
-        part = d0[i];
+        const uint64_t w = d0[i];
+        if ((w >> kL2Shift) != 0) {  // unfinished
+          val[i] += w & kL2Mask;
+          a = pa;
+          part = true;
+        }
       }
-      if (unfinished) {
-        val[i] += part;
-        a = pa;
-      }
+      anc[i] = a;
+      d0[i] = 0;
+      d1[i] = 0;
+      more |= a >= 0;
     }
-    anc[i] = a;
-    d0[i] = 0;
-    d1[i] = 0;
-    more |= a >= 0;
+    if (plist) append_node(plist, &hdr[4], (int32_t)i, part);
   }
   if (more) hdr[64] = 1;
 }
 
 template <typename V>
-__global__ void k_l2_round(int j, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1, uint32_t* hdr) {
+__global__ void k_l2_round(int j, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1, const int32_t* plist,
+                           uint32_t* hdr) {
   if (hdr[64 + j] == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && hdr[1] == 0xFFFFFFFFu) hdr[1] = (uint32_t)(j & 1);
     return;
   }
-  const int64_t n = hdr[3];
+  const int64_t m = plist ? hdr[4] : hdr[3];
   V* dc = (j & 1) ? d1 : d0;
   V* dn = (j & 1) ? d0 : d1;
   const int32_t* ac = (j & 1) ? a1 : a0;
   int32_t* an = (j & 1) ? a0 : a1;
   bool more = false;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = plist ? plist[t] : (int32_t)t;
     const int32_t a = ac[i];
     const V d = dc[i];
     if (a < 0 && d == (V)0) {  // nothing to fold or send
@@ -1575,13 +1595,16 @@ __global__ void k_l2_round(int j, V* val, V* d0, V* d1, int32_t* a0, int32_t* a1
   if (more) hdr[64 + j + 1] = 1;
 }
 
-// Adds the last pending increment: the resolved value of every node.
+// Adds the last pending increment: the resolved value of every listed node
+// (the others hold theirs already).
 template <typename V>
-__global__ void k_l2_fold(V* val, const V* d0, const V* d1, const uint32_t* hdr) {
-  const int64_t n = hdr[3];
+__global__ void k_l2_fold(V* val, const V* d0, const V* d1, const int32_t* plist, const uint32_t* hdr) {
+  const int64_t m = plist ? hdr[4] : hdr[3];
   const V* d = (hdr[1] & 1) ? d1 : d0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = plist ? plist[t] : (int32_t)t;
     val[i] += d[i];
+  }
 }
 
 // Backward: path sums H(e) = w(e) + H(parent(e)), w(e) = the receiver's
@@ -1893,11 +1916,12 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
   // atomics (an L2 write-back on this GPU) per step; doubling does it all.
   if constexpr (std::is_same<V, uint64_t>::value)
     hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
-  hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, p.hdr);
+  int32_t* pl = std::is_same<V, uint64_t>::value ? p.plist : nullptr;
+  hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, pl, p.hdr);
   for (int j = 0; j < p.rounds; ++j)
-    hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, p.hdr);
+    hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, pl, p.hdr);
   hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
-  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, p.hdr);
+  hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, pl, p.hdr);
   group_pass<LV, V, true>(p, s);
   return hipGetLastError();
 }
