@@ -37,8 +37,12 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, vo
   size_t o_buf[3], o_anc[2];
   for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
   for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
-  const size_t o_list = take((size_t)p.nslots * 4);
-  const size_t o_plist = take((size_t)p.nslots * 4);
+  // the backward layout (ncells > 0) pads the two lists for its segmented
+  // exit lists and adds their segment lengths
+  const int64_t pad = ncells > 0 ? list_pad(p.nslots) : 0;
+  const size_t o_list = take((size_t)(p.nslots + pad) * 4);
+  const size_t o_plist = take((size_t)(p.nslots + pad) * 4);
+  const size_t o_lcnt = ncells > 0 ? take((size_t)2 * kListGrid * 4) : 0;
   const size_t o_blo = ncells > 0 ? take((size_t)ncells * 4) : 0;
   const size_t o_broot = ncells > 0 ? take((size_t)ncells * 2) : 0;
   p.bytes = off;
@@ -53,6 +57,7 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, vo
     for (int i = 0; i < 2; ++i) p.anc[i] = reinterpret_cast<int32_t*>(b + o_anc[i]);
     p.list = reinterpret_cast<int32_t*>(b + o_list);
     p.plist = reinterpret_cast<int32_t*>(b + o_plist);
+    p.lcnt = ncells > 0 ? reinterpret_cast<uint32_t*>(b + o_lcnt) : nullptr;
     p.blo = ncells > 0 ? reinterpret_cast<float*>(b + o_blo) : nullptr;
     p.broot = ncells > 0 ? reinterpret_cast<uint16_t*>(b + o_broot) : nullptr;
   }
@@ -292,7 +297,7 @@ static d8_status run_forward(const Plan& p, const uint8_t* dirs, const float* w,
 
 static d8_status run_backward(const Plan& p, const uint8_t* dirs, const float* g, float* gw, hipStream_t s) {
   if (p.ts > 64) return D8_EUNSUPPORTED;
-  if (!p.broot || !p.blo) return D8_EINVAL;
+  if (!p.broot || !p.blo || !p.lcnt) return D8_EINVAL;
   hipError_t e = launch_zero_header(p.hdr, s);
   if (e != hipSuccess) return D8_EHIP;
   {

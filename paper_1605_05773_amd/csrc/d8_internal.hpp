@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -24,9 +26,14 @@ namespace d8 {
 //   anc[2]   int32  x nslots   resolve ancestor pointers (forward: anc[0] the
 //                              nodes' ancestors by node id, anc[1] every tile
 //                              exit's super-block root node id)
-//   list     int32  x nslots   forward: second ancestor buffer of the nodes
-//   plist    int32  x nslots   forward: the nodes taking part in the
-//                              doubling stage of the global resolve
+//   list     int32  x nslots   forward: second ancestor buffer of the nodes;
+//                              backward: exit list of even rounds
+//   plist    int32  x nslots   forward: the nodes taking part in the doubling
+//                              stage of the global resolve; backward: exit
+//                              list of odd rounds (the backward layout pads
+//                              both lists by list_pad() entries)
+//   lcnt     uint32 x 2 kListGrid   backward: per workgroup, the length of its
+//                              segment of the two exit lists
 //   blo      float  x ncells   backward: per cell, the low part of its fp64
 //                              in-tile path sum (the high part is held in the
 //                              output between the two tile passes)
@@ -53,6 +60,7 @@ struct Plan {
   int64_t nsb = 0;     // super-blocks (kSuper x kSuper cells)
   int32_t* list = nullptr;  // second ancestor buffer of the super-block exit nodes
   int32_t* plist = nullptr;  // nodes of the doubling stage of the global resolve
+  uint32_t* lcnt = nullptr;  // backward: segment lengths of the exit lists
   DemTable tab{};
   uint32_t* hdr = nullptr;
   DemInfo* demtab = nullptr;
@@ -67,6 +75,17 @@ struct Plan {
 };
 
 constexpr size_t kHdrBytes = 4096;
+// Backward resolve: list_grid() workgroups (one per 256 slots, at most
+// kListGrid: enough threads in flight for its chains of dependent loads), each
+// with a segment of the exit lists of list_segment() entries (a multiple of
+// its 256 threads), so the lists need list_pad() entries beyond nslots.
+constexpr int kListGrid = 16384;
+inline int64_t list_grid(int64_t nslots) { return std::min<int64_t>((nslots + 255) / 256, kListGrid); }
+inline int64_t list_pad(int64_t nslots) { return list_grid(nslots) * 256; }
+inline int64_t list_segment(int64_t nslots, int64_t grid) {
+  const int64_t per = (nslots + grid * 256 - 1) / (grid * 256);
+  return per * 256;
+}
 constexpr int kMaxRounds = 62;
 
 // ncells: packed cells the backward's per-cell exit array covers (0: none).

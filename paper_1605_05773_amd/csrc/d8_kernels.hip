@@ -1608,47 +1608,103 @@ __global__ void k_l2_fold(V* val, const V* d0, const V* d1, const int32_t* plist
 }
 
 // Backward: path sums H(e) = w(e) + H(parent(e)), w(e) = the receiver's
-// in-tile path sum, by pointer jumping (Wyllie).  Two buffers each.
-__global__ void k_bres_init(DemTable tab, int ts, int cap, int64_t nslots, const uint8_t* __restrict__ ex_code,
-                            const uint16_t* __restrict__ rl, const double* __restrict__ rg, double* b0, int32_t* a0,
-                            uint32_t* hdr) {
+// in-tile path sum, by pointer jumping (Wyllie) over the exit slots, with two
+// value and two ancestor buffers used alternately.  An exit whose ancestor
+// runs out is done: its value is final in the buffer the round wrote, and it
+// copies it into the other one in the next round (ancestor code -2), after
+// which both hold it and the exit drops out (code -1).  The exits still in
+// play are listed: workgroup w of the fixed grid keeps its own segment
+// [w * seg, (w + 1) * seg) of the list of a round (L0 for even rounds, L1 for
+// odd ones) with its length in cnt (cnt[w] for even rounds, cnt[G + w] for
+// odd ones), so a round touches only the listed exits and appends the ones
+// still in play with LDS counters (no global atomics).
+
+// Appends v to the workgroup's segment `out` when `take`; n: LDS counter.
+__device__ __forceinline__ void append_local(int32_t* out, uint32_t* n, int32_t v, bool take) {
+  const uint64_t m = __builtin_amdgcn_ballot_w64(take);
+  if (m == 0) return;
+  const int lane = (int)__lane_id();
+  const int leader = __builtin_ctzll(m);
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(n, (uint32_t)__builtin_popcountll(m));
+  base = __shfl(base, leader);
+  if (take) out[base + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1))] = v;
+}
+
+__global__ __launch_bounds__(256) void k_bres_init(DemTable tab, int ts, int cap, int64_t nslots,
+                                                   const uint8_t* __restrict__ ex_code,
+                                                   const uint16_t* __restrict__ rl, const double* __restrict__ rg,
+                                                   double* b0, int32_t* a0, int32_t* L0, int64_t seg, uint32_t* cnt,
+                                                   uint32_t* hdr) {
+  __shared__ uint32_t ln;
+  if (threadIdx.x == 0) ln = 0;
+  __syncthreads();
+  int32_t* mine = L0 + blockIdx.x * seg;
   bool more = false;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
-    const uint8_t ec = ex_code[s];
-    if (ec >= 8) continue;
-    int64_t tslot;
-    int32_t par;
-    more |= exit_parent(tab, s, ts, cap, ec, rl, tslot, par);
-    a0[s] = par;
-    b0[s] = rg[tslot];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t s0 = blockIdx.x * (int64_t)blockDim.x; s0 < nslots; s0 += stride) {
+    const int64_t s = s0 + threadIdx.x;
+    bool exit = false;
+    if (s < nslots) {
+      const uint8_t ec = ex_code[s];
+      if (ec < 8) {
+        exit = true;
+        int64_t tslot;
+        int32_t par;
+        const bool has = exit_parent(tab, s, ts, cap, ec, rl, tslot, par);
+        more |= has;
+        a0[s] = has ? par : -2;
+        b0[s] = rg[tslot];
+      }
+    }
+    append_local(mine, &ln, (int32_t)s, exit);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[blockIdx.x] = ln;
   if (more) hdr[64] = 1;
 }
 
-__global__ void k_bres_round(int j, int64_t nslots, const uint8_t* __restrict__ ex_code, double* b0, double* b1,
-                             int32_t* a0, int32_t* a1, uint32_t* hdr) {
+__global__ __launch_bounds__(256) void k_bres_round(int j, double* b0, double* b1, int32_t* a0, int32_t* a1,
+                                                    int32_t* L0, int32_t* L1, int64_t seg, uint32_t* cnt,
+                                                    uint32_t* hdr) {
   if (hdr[64 + j] == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && hdr[2] == 0xFFFFFFFFu) hdr[2] = (uint32_t)(j & 1);
     return;
   }
+  __shared__ uint32_t ln;
+  if (threadIdx.x == 0) ln = 0;
+  __syncthreads();
   const double* cur = (j & 1) ? b1 : b0;
   double* nxt = (j & 1) ? b0 : b1;
   const int32_t* ac = (j & 1) ? a1 : a0;
   int32_t* an = (j & 1) ? a0 : a1;
+  const int64_t G = gridDim.x;
+  const int32_t* Lc = ((j & 1) ? L1 : L0) + blockIdx.x * seg;
+  int32_t* Ln = ((j & 1) ? L0 : L1) + blockIdx.x * seg;
+  const uint32_t m = cnt[((j & 1) ? G : 0) + blockIdx.x];
   bool more = false;
-  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < nslots; s += (int64_t)gridDim.x * blockDim.x) {
-    if (ex_code[s] >= 8) continue;
-    const int32_t a = ac[s];
-    if (a >= 0) {
-      nxt[s] = cur[s] + cur[a];
-      const int32_t a2 = ac[a];
-      an[s] = a2;
-      more |= a2 >= 0;
-    } else {
-      nxt[s] = cur[s];
-      an[s] = -1;
+  for (uint32_t t0 = 0; t0 < m; t0 += blockDim.x) {
+    const uint32_t t = t0 + threadIdx.x;
+    bool keep = false;
+    int32_t s = 0;
+    if (t < m) {
+      s = Lc[t];
+      const int32_t a = ac[s];
+      if (a >= 0) {
+        nxt[s] = cur[s] + cur[a];
+        const int32_t a2 = ac[a];
+        an[s] = a2 >= 0 ? a2 : -2;
+        more |= a2 >= 0;
+        keep = true;
+      } else {  // done in the last round: copy the final value, then drop out
+        nxt[s] = cur[s];
+        an[s] = -1;
+      }
     }
+    append_local(Ln, &ln, s, keep);
   }
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[((j & 1) ? 0 : G) + blockIdx.x] = ln;
   if (more) hdr[64 + j + 1] = 1;
 }
 
@@ -1934,13 +1990,16 @@ hipError_t launch_backward_resolve(const Plan& p, hipStream_t s) {
   double* b0 = reinterpret_cast<double*>(p.buf[0]);
   double* b1 = reinterpret_cast<double*>(p.buf[1]);
   const double* rg = reinterpret_cast<const double*>(p.ex_val);
-  const unsigned g = grid_for(p.nslots, 256);
+  // the same workgroups for the init and every round, each with its own
+  // segment of the exit lists (list_grid, as the layout sized them)
+  const unsigned gr = (unsigned)std::max<int64_t>(1, list_grid(p.nslots));
+  const int64_t seg = list_segment(p.nslots, gr);
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
-  hipLaunchKernelGGL(k_bres_init, dim3(g), dim3(256), 0, s, p.tab, p.ts, p.cap, p.nslots, p.ex_code, p.rl, rg, b0,
-                     p.anc[0], p.hdr);
+  hipLaunchKernelGGL(k_bres_init, dim3(gr), dim3(256), 0, s, p.tab, p.ts, p.cap, p.nslots, p.ex_code, p.rl, rg, b0,
+                     p.anc[0], p.list, seg, p.lcnt, p.hdr);
   for (int j = 0; j < p.rounds; ++j)
-    hipLaunchKernelGGL(k_bres_round, dim3(g), dim3(256), 0, s, j, p.nslots, p.ex_code, b0, b1, p.anc[0], p.anc[1],
-                       p.hdr);
+    hipLaunchKernelGGL(k_bres_round, dim3(gr), dim3(256), 0, s, j, b0, b1, p.anc[0], p.anc[1], p.list, p.plist, seg,
+                       p.lcnt, p.hdr);
   hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 2, 2, p.hdr, p.hdr);
   return hipGetLastError();
 }
