@@ -1974,9 +1974,14 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
     hipLaunchKernelGGL((k_l2_walk<V>), dim3(gn), dim3(256), 0, s, p.anc[0], b0, b1, pend, p.hdr);
   int32_t* pl = std::is_same<V, uint64_t>::value ? p.plist : nullptr;
   hipLaunchKernelGGL((k_l2_prep<V>), dim3(g), dim3(256), 0, s, p.anc[0], b0, b1, b2, pend, pl, p.hdr);
-  for (int j = 0; j < p.rounds; ++j)
+  // a forest of at most maxn nodes is done after floor(log2(maxn)) + 1
+  // doubling rounds; flags still set after them mean a cycle
+  int rounds = 1;
+  while (((int64_t)1 << (rounds - 1)) <= maxn && rounds < kMaxRounds) ++rounds;
+  rounds = std::min(rounds, p.rounds);
+  for (int j = 0; j < rounds; ++j)
     hipLaunchKernelGGL((k_l2_round<V>), dim3(g), dim3(256), 0, s, j, b0, b1, b2, p.anc[0], p.list, pl, p.hdr);
-  hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, p.rounds, 1, 2, p.hdr, p.hdr);
+  hipLaunchKernelGGL(k_res_finish, dim3(1), dim3(1), 0, s, rounds, 1, 2, p.hdr, p.hdr);
   hipLaunchKernelGGL((k_l2_fold<V>), dim3(g), dim3(256), 0, s, b0, b1, b2, pl, p.hdr);
   group_pass<LV, V, true>(p, s);
   return hipGetLastError();
