@@ -1088,6 +1088,15 @@ __device__ __forceinline__ void vadd(uint64_t* p, uint64_t v) {
 }
 __device__ __forceinline__ void vadd(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// Level-2 node state of the counts resolve: one 64-bit word per node, bits
+// 0..39 the sum received, bits 40..62 the children still to arrive (see the
+// global resolve below).
+constexpr int kL2Shift = 40;
+constexpr uint64_t kL2One = 1ull << kL2Shift;
+constexpr uint64_t kL2Mask = kL2One - 1;
+constexpr uint32_t kL2HasKids = 0x80000000u;
+constexpr int kL2Steps = 32;
+
 // ------------------------------------------------ super-block group pass --
 // The tile exits of a kSuper x kSuper super-block form a forest whose edges
 // stay inside the super-block except at its own exits.  One workgroup
@@ -1374,6 +1383,71 @@ __global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, i
     D8_STAMP(DOWN ? 3 : 2, 5);
     return;
   }
+  // Counts: each super-block exit's number of children in the global forest
+  // (the walk stage retires them one by one): the exits of neighbouring
+  // super-blocks that drain into a border receiver here whose path leads to
+  // that exit.  The codes of those neighbours are final (the tile pass wrote
+  // them), so they are counted here, in LDS, with no global atomics; the
+  // values move to registers and `val` holds the counts meanwhile.
+  constexpr bool kKids = std::is_same<V, uint64_t>::value;
+  LV vown[kKids ? NPT : 1];
+  if constexpr (kKids) {
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int n = tid + k * NT;
+      vown[k] = n < NN ? val[n] : (LV)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k)
+      if (tid + k * NT < NN) val[tid + k * NT] = 0;
+    // the border cells' outside neighbours draining into them, and the tile
+    // exit each border cell's own path leaves by (loads issued together)
+    const int P = perim_count(sbw, sbh);
+    uint32_t nkid[NPB];
+    int node[NPB];
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      const int i = tid + q * NT;
+      int r = 0, c = 0;
+      if (i < P) perim_cell(i, sbw, sbh, r, c);
+      const int64_t gy = y0 + r, gx = x0 + c;
+      const uint32_t out = i < P ? outside_dirs(r, c, sbw, sbh) : 0u;
+      uint8_t e[8];
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        e[d] = 0xFF;
+        const int64_t ny = gy + ddr_t(d), nx = gx + ddc_t(d);
+        if ((out & (1u << d)) && ny >= 0 && ny < dm.H && nx >= 0 && nx < dm.W)
+          e[d] = ex_code[slot_of_cell(dm, ny, nx, TS, CAP)];
+      }
+      uint16_t lk = 0xFFFF;
+      int tnode = 0;
+      if (out) {
+        const int64_t tty = gy / TS, ttx = gx / TS;
+        const int tth = (int)min((int64_t)TS, (int64_t)dm.H - tty * TS);
+        const int ttw = (int)min((int64_t)TS, (int64_t)dm.W - ttx * TS);
+        const int rs = perim_slot((int)(gy - tty * TS), (int)(gx - ttx * TS), ttw, tth);
+        lk = rl[(dm.tile0 + tty * dm.TX + ttx) * CAP + rs];
+        tnode = (int)(((tty - ty0) * G + (ttx - tx0)) * CAP);
+      }
+      uint32_t k = 0;
+#pragma unroll
+      for (int d = 0; d < 8; ++d)  // a neighbour counts if its exit step lands on this cell
+        k += (e[d] < 8 && ddr_t(e[d]) == -ddr_t(d) && ddc_t(e[d]) == -ddc_t(d)) ? 1u : 0u;
+      nkid[q] = k;
+      node[q] = (k && lk != 0xFFFF) ? tnode + lk : -1;
+    }
+    __syncthreads();  // every count zeroed
+#pragma unroll
+    for (int q = 0; q < NPB; ++q) {
+      if (node[q] < 0) continue;
+      const int rt = (int)(link[node[q]] >> 16);  // the super-block root of that tile exit
+      if (flag[rt] & 2) atomicAdd(&val[rt], (LV)nkid[q]);
+    }
+    __syncthreads();
+  }
+
   // Dense node ids for the super-block exits: one global atomic per
   // workgroup, offsets from an LDS counter.
   uint32_t nsx = 0;  // own nodes that leave the super-block
@@ -1399,9 +1473,14 @@ __global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, i
     if (nsx & (1u << k)) {
       const int n = tid + k * NT;
       link[n] = w;  // node id, looked up by the tile exits rooted here
-      l2val[w] = (V)val[n];
+      if constexpr (kKids) {
+        l2val[w] = (V)vown[k];
+        l2acc[w] = (V)val[n] << kL2Shift;  // children still to arrive, nothing received
+      } else {
+        l2val[w] = (V)val[n];
+        l2acc[w] = 0;
+      }
       l2par[w] = tg[k];
-      l2acc[w] = 0;
       l2pend[w] = 0;
       ++w;
     }
@@ -1442,29 +1521,14 @@ __global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, i
 // sum received, bits 40..62 the children still to arrive); weighted values
 // keep an fp64 sum and a pending count whose bit 31 marks a node with
 // children, a child's addition being fenced before its retirement.
-constexpr int kL2Shift = 40;
-constexpr uint64_t kL2One = 1ull << kL2Shift;
-constexpr uint64_t kL2Mask = kL2One - 1;
-constexpr uint32_t kL2HasKids = 0x80000000u;
-constexpr int kL2Steps = 32;
 
 // Parent ids: -1 root; <= -2 a parked node (parent -(p + 2)).
-template <typename V>
-__global__ void k_l2_init(const int32_t* __restrict__ sbroot, int32_t* par, V* acc, uint64_t* pend, uint32_t* hdr) {
+// Parent of every node (the children were counted by the super-block pass).
+__global__ void k_l2_init(const int32_t* __restrict__ sbroot, int32_t* par, const uint32_t* hdr) {
   const int64_t n = hdr[3];
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t v = par[i];  // the tile exit the target receiver leads to
-    const int32_t pa = v >= 0 ? sbroot[v] : -1;
-    par[i] = pa;
-    if (pa >= 0) {
-      if constexpr (std::is_same<V, uint64_t>::value) {
-        atomicAdd(&acc[pa], kL2One);
-      } else {
-        uint32_t* pc = reinterpret_cast<uint32_t*>(&pend[pa]);
-        atomicOr(pc, kL2HasKids);
-        atomicAdd(pc, 1u);
-      }
-    }
+    par[i] = v >= 0 ? sbroot[v] : -1;
   }
 }
 
@@ -1967,7 +2031,7 @@ static hipError_t fres(const Plan& p, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(128), 0, s, p.hdr);
   group_pass<LV, V, false>(p, s);
   uint64_t* pend = p.buf[2];
-  hipLaunchKernelGGL((k_l2_init<V>), dim3(g), dim3(256), 0, s, p.anc[1], p.anc[0], b1, pend, p.hdr);
+  hipLaunchKernelGGL(k_l2_init, dim3(g), dim3(256), 0, s, p.anc[1], p.anc[0], p.hdr);
   // Counts only: the weighted stage 1 would need a fence between its two
   // atomics (an L2 write-back on this GPU) per step; doubling does it all.
   if constexpr (std::is_same<V, uint64_t>::value)
