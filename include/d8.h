@@ -132,7 +132,7 @@ d8_status d8_accum(const uint8_t* dirs, int64_t rows, int64_t cols, const float*
  * (D8_NOALLOC_SCRATCH_BYTES per GPU; each GPU the library runs on holds it
  * until the process ends) instead of a caller workspace; the call allocates
  * nothing.  Shapes whose d8_workspace_bytes exceed the array (at tile 64
- * about 3.2 bytes per cell, so up to about 4600 x 4600 cells) return
+ * about 1.9 bytes per cell, so up to about 5900 x 5900 cells) return
  * D8_ENOMEM and enqueue nothing.  Every call on one GPU uses that GPU's array:
  * calls that overlap in time on one GPU (concurrent streams, threads) race.
  * status: NULL, or a device uint32 that receives, on `stream` after the

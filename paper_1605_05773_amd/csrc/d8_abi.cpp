@@ -15,7 +15,7 @@ namespace d8 {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, void* base) {
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t nsb, int64_t ncells, void* base) {
   p.ts = ts;
   p.cap = 4 * ts - 4;
   p.ntiles = ntiles;
@@ -34,14 +34,20 @@ size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, vo
   const size_t o_code = take((size_t)p.nslots);
   const size_t o_rl = take((size_t)p.nslots * 2);
   const size_t o_val = take((size_t)p.nslots * 8);
-  size_t o_buf[3], o_anc[2];
-  for (int i = 0; i < 3; ++i) o_buf[i] = take((size_t)p.nslots * 8);
-  for (int i = 0; i < 2; ++i) o_anc[i] = take((size_t)p.nslots * 4);
-  // the backward layout (ncells > 0) pads the two lists for its segmented
-  // exit lists and adds their segment lengths
+  // The forward's level-2 arrays (buf[0], buf[1], anc[0], list, plist) are
+  // indexed by super-block exit node: at most one per super-block perimeter
+  // cell.  The backward (ncells > 0) indexes them by exit slot, and pads the
+  // two lists for its segmented exit lists.
+  const int64_t nnode = ncells > 0 ? p.nslots : std::min<int64_t>(p.nslots, nsb * 4 * kSuper);
   const int64_t pad = ncells > 0 ? list_pad(p.nslots) : 0;
-  const size_t o_list = take((size_t)(p.nslots + pad) * 4);
-  const size_t o_plist = take((size_t)(p.nslots + pad) * 4);
+  size_t o_buf[3], o_anc[2];
+  o_buf[0] = take((size_t)nnode * 8);
+  o_buf[1] = take((size_t)nnode * 8);
+  o_buf[2] = take((size_t)p.nslots * 8);  // also the inflow of every receiver slot
+  o_anc[0] = take((size_t)nnode * 4);
+  o_anc[1] = take((size_t)p.nslots * 4);  // every tile exit's super-block root
+  const size_t o_list = take((size_t)(nnode + pad) * 4);
+  const size_t o_plist = take((size_t)(nnode + pad) * 4);
   const size_t o_lcnt = ncells > 0 ? take((size_t)2 * kListGrid * 4) : 0;
   const size_t o_blo = ncells > 0 ? take((size_t)ncells * 4) : 0;
   const size_t o_broot = ncells > 0 ? take((size_t)ncells * 2) : 0;
@@ -225,12 +231,16 @@ d8_status d8_flowdirs_steepest(const float* dem, int64_t rows, int64_t cols, uin
   return flowdirs_rule(dem, rows, cols, dirs, stream, true);
 }
 
+static int64_t super_blocks(int64_t rows, int64_t cols) {
+  return ((rows + kSuper - 1) / kSuper) * ((cols + kSuper - 1) / kSuper);
+}
+
 size_t d8_workspace_bytes(int64_t rows, int64_t cols, int tile) {
   const int ts = pick_tile(tile);
   if (!ts || !shape_ok(rows, cols)) return 0;
   Plan p;
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
-  return plan_layout(p, nt, ts, 1, 0, nullptr);
+  return plan_layout(p, nt, ts, 1, super_blocks(rows, cols), 0, nullptr);
 }
 
 size_t d8_backward_workspace_bytes(int64_t rows, int64_t cols, int tile) {
@@ -238,7 +248,7 @@ size_t d8_backward_workspace_bytes(int64_t rows, int64_t cols, int tile) {
   if (!ts || !shape_ok(rows, cols)) return 0;
   Plan p;
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
-  return plan_layout(p, nt, ts, 1, rows * cols, nullptr);
+  return plan_layout(p, nt, ts, 1, super_blocks(rows, cols), rows * cols, nullptr);
 }
 
 // backward: the workspace also holds the per-cell exit array.
@@ -249,8 +259,8 @@ static d8_status prep_single(Plan& p, int64_t rows, int64_t cols, void* ws, size
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
   const int64_t nt = ((rows + ts - 1) / ts) * ((cols + ts - 1) / ts);
   const int64_t nc = backward ? rows * cols : 0;
-  if (plan_layout(p, nt, ts, 1, nc, nullptr) > ws_bytes) return D8_ENOMEM;
-  plan_layout(p, nt, ts, 1, nc, ws);
+  if (plan_layout(p, nt, ts, 1, super_blocks(rows, cols), nc, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, 1, super_blocks(rows, cols), nc, ws);
   set_blocks(p, nullptr, 1, rows, cols, 0);
   p.tab.n = 1;
   p.tab.dev = nullptr;
@@ -603,6 +613,12 @@ static int64_t batch_span(const d8_desc* hd, int32_t n) {
   return e;
 }
 
+static int64_t batch_super_blocks(const d8_desc* hd, int32_t n) {
+  int64_t b = 0;
+  for (int32_t i = 0; i < n; ++i) b += super_blocks(hd[i].rows, hd[i].cols);
+  return b;
+}
+
 size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile) {
   const int ts = pick_tile(tile);
   int64_t nt;
@@ -610,7 +626,7 @@ size_t d8_batched_workspace_bytes(const d8_desc* host_desc, int32_t n, int tile)
   int64_t ntf;
   batch_tiles(host_desc, n, kFlowdirsBlock, ntf);
   Plan p;
-  size_t b = plan_layout(p, nt, ts, n, 0, nullptr);
+  size_t b = plan_layout(p, nt, ts, n, batch_super_blocks(host_desc, n), 0, nullptr);
   return std::max(b, align256(kHdrBytes) + align256(sizeof(DemInfo) * (size_t)n));
 }
 
@@ -619,7 +635,7 @@ size_t d8_batched_backward_workspace_bytes(const d8_desc* host_desc, int32_t n, 
   int64_t nt;
   if (!ts || !batch_tiles(host_desc, n, ts, nt)) return 0;
   Plan p;
-  return plan_layout(p, nt, ts, n, batch_span(host_desc, n), nullptr);
+  return plan_layout(p, nt, ts, n, batch_super_blocks(host_desc, n), batch_span(host_desc, n), nullptr);
 }
 
 static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int32_t n, void* ws, size_t ws_bytes,
@@ -628,8 +644,9 @@ static d8_status prep_batched(Plan& p, const d8_desc* hd, const d8_desc* dd, int
   if (!ts || !dd || !ws || !batch_tiles(hd, n, ts, nt)) return D8_EINVAL;
   if (reinterpret_cast<uintptr_t>(ws) & 255) return D8_EINVAL;
   const int64_t nc = backward ? batch_span(hd, n) : 0;
-  if (plan_layout(p, nt, ts, n, nc, nullptr) > ws_bytes) return D8_ENOMEM;
-  plan_layout(p, nt, ts, n, nc, ws);
+  const int64_t nsb = batch_super_blocks(hd, n);
+  if (plan_layout(p, nt, ts, n, nsb, nc, nullptr) > ws_bytes) return D8_ENOMEM;
+  plan_layout(p, nt, ts, n, nsb, nc, ws);
   set_blocks(p, hd, n, 0, 0, waves, counts);
   if (n == 1) {
     p.tab.n = 1;

@@ -20,18 +20,22 @@ namespace d8 {
 //   rl       uint16 x nslots   receiver slot -> exit slot of its in-tile path
 //   ex_val   8 B    x nslots   exit partial value (forward) / receiver path
 //                              sum (backward)
-//   buf[3]   8 B    x nslots   resolve values (forward: [0] values of the
-//                              super-block exits by dense node id, [1] and
-//                              [2] their pending increments)
-//   anc[2]   int32  x nslots   resolve ancestor pointers (forward: anc[0] the
-//                              nodes' ancestors by node id, anc[1] every tile
-//                              exit's super-block root node id)
-//   list     int32  x nslots   forward: second ancestor buffer of the nodes;
+//   buf[3]   8 B    x nnode, nnode, nslots   resolve values (forward: [0]
+//                              values of the super-block exits by dense node
+//                              id, [1] and [2] their pending increments; [2]
+//                              then the inflow of every receiver slot)
+//   anc[2]   int32  x nnode, nslots   resolve ancestor pointers (forward:
+//                              anc[0] the nodes' ancestors by node id, anc[1]
+//                              every tile exit's super-block root node id)
+//   list     int32  x nnode    forward: second ancestor buffer of the nodes;
 //                              backward: exit list of even rounds
-//   plist    int32  x nslots   forward: the nodes taking part in the doubling
+//   plist    int32  x nnode    forward: the nodes taking part in the doubling
 //                              stage of the global resolve; backward: exit
 //                              list of odd rounds (the backward layout pads
 //                              both lists by list_pad() entries)
+// nnode: the forward's level-2 nodes, at most one per super-block perimeter
+// cell (nsb * 4 * kSuper); the backward indexes these arrays by exit slot
+// (nnode = nslots).
 //   lcnt     uint32 x 2 kListGrid   backward: per workgroup, the length of its
 //                              segment of the two exit lists
 //   blo      float  x ncells   backward: per cell, the low part of its fp64
@@ -88,8 +92,9 @@ inline int64_t list_segment(int64_t nslots, int64_t grid) {
 }
 constexpr int kMaxRounds = 62;
 
-// ncells: packed cells the backward's per-cell exit array covers (0: none).
-size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t ncells, void* base);
+// nsb: super-blocks (bounds the forward's level-2 nodes); ncells: packed
+// cells the backward's per-cell arrays cover (0: the forward layout).
+size_t plan_layout(Plan& p, int64_t ntiles, int ts, int ndem, int64_t nsb, int64_t ncells, void* base);
 
 // Launchers (return hipError_t of the last launch).
 // Flow directions over 64x64-cell blocks (tab built with tile side 64).

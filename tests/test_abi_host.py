@@ -82,7 +82,7 @@ def test_argument_errors_before_device_work():
     assert L.d8_accum_noalloc(fake, 10, 10, fake, d8.D8_U32, fake, None, 0, None, None) == d8.D8_EINVAL
     assert L.d8_accum_noalloc(fake, 0, 10, None, d8.D8_U32, fake, None, 0, None, None) == d8.D8_EINVAL
     assert L.d8_accum_noalloc(fake, 8192, 8192, None, d8.D8_U32, fake, None, 0, None, None) == d8.D8_ENOMEM
-    assert L.d8_workspace_bytes(4600, 4600, 64) <= 64 << 20 < L.d8_workspace_bytes(8192, 8192, 64)
+    assert L.d8_workspace_bytes(5900, 5900, 64) <= 64 << 20 < L.d8_workspace_bytes(8192, 8192, 64)
 
 
 def test_batched_workspace_validation():
