@@ -411,7 +411,7 @@ __device__ __forceinline__ BlockGeo block_geo(const DemTable& tab, int64_t blk) 
 // precision).  The pass writes the tile-local areas to the output and the
 // perimeter records of every tile; the finalising pass adds the inflows.
 template <int BW, int BH, int TS, typename V, int CPT>
-__global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
+__global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(CPT == 8 ? 8 : 1))) void k_block_emit(
     const uint8_t* __restrict__ dirs, const float* __restrict__ w, DemTable tab, int64_t nblocks, int cap,
     uint8_t* __restrict__ ex_code, uint16_t* __restrict__ rl, void* __restrict__ ex_val, void* __restrict__ out,
     float* __restrict__ out_lo, uint32_t* __restrict__ status, const float* __restrict__ dem,
@@ -446,47 +446,107 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
   }
   D8_STAMP(0, 1);
 
-  // Setup: in-tile target (ancestor at distance 1) and initial value.  Only
-  // blocks on the DEM's border can have targets off the grid.
+  // Setup: in-tile target (ancestor at distance 1), the target's own target
+  // (distance 2) and the initial value.  Every code a thread needs is read
+  // before any is used (one LDS round trip per distance, not one per cell).
+  // Only blocks on the DEM's border can have targets off the grid.
   const bool border = g.y0 == 0 || g.x0 == 0 || g.y0 + BH >= g.dm.H || g.x0 + BW >= g.dm.W;
-  uint16_t a[CPT];
+  // Cells are taken in batches of SB (register pressure).
+  constexpr int SB = CPT < 4 ? CPT : 4;
+  bool bad = false;
+  uint16_t a[CPT], a1[CPT];
+  V v0[CPT];
+  bool more = false;
 #pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    const int c = tid + k * NT;
-    const int r = c / BW, col = c % BW;
-    const uint32_t code = sm.code[(r + 1) * HS + col + 1];
-    const bool ok = r < g.bh && col < g.bw && code != kNoData;
-    const uint32_t d = code & 7u;
-    const int dr = ddr_t(d), dc = ddc_t(d);
-    const int ta = r / TS, tb = col / TS;
-    const int th = min(TS, g.bh - ta * TS), tw = min(TS, g.bw - tb * TS);
-    const int tr = r - ta * TS + dr, tc = col - tb * TS + dc;
-    const bool drains = ok && code < 8u;
-    const bool inside = drains && tr >= 0 && tr < th && tc >= 0 && tc < tw;
-    const uint8_t tcode = sm.code[(r + 1 + dr) * HS + col + 1 + dc];
-    bool bad = ok && (code > 8u || (drains && tcode == kNoData));
-    if (border)
-      bad |= drains && !inside &&
-             (g.y0 + r + dr < 0 || g.y0 + r + dr >= g.dm.H || g.x0 + col + dc < 0 || g.x0 + col + dc >= g.dm.W);
-    if (bad) set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
-    a[k] = (inside && tcode != kNoData) ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
-    if constexpr (kCount)
-      sm.val[c] = ok ? 1u : 0u;
-    else
-      sm.val[c] = ok ? (double)wv[k] : 0.0;
-    sm.link[c] = (uint32_t)a[k] | ((uint32_t)(a[k] != kNoAnc ? a[k] : (uint16_t)c) << 16);
+  for (int h = 0; h < CPT; h += SB) {
+    uint32_t cd[SB], td[SB], ud[SB];
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int c = tid + (h + q) * NT;
+      const int r = c / BW, col = c % BW;
+      cd[q] = sm.code[(r + 1) * HS + col + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int c = tid + (h + q) * NT;
+      const int r = c / BW, col = c % BW;
+      const uint32_t d = cd[q] & 7u;
+      td[q] = sm.code[(r + 1 + ddr_t(d)) * HS + col + 1 + ddc_t(d)];
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int c = tid + (h + q) * NT;
+      const int r = c / BW, col = c % BW;
+      const uint32_t d = cd[q] & 7u, e = td[q] & 7u;
+      // two steps can leave the halo: clamped (the code read is then unused)
+      const int ur = min(max(r + 1 + ddr_t(d) + ddr_t(e), 0), BH + 1);
+      const int uc = min(max(col + 1 + ddc_t(d) + ddc_t(e), 0), BW + 1);
+      ud[q] = sm.code[ur * HS + uc];
+    }
+#pragma unroll
+    for (int q = 0; q < SB; ++q) {
+      const int k = h + q;
+      const int c = tid + k * NT;
+      const int r = c / BW, col = c % BW;
+      const uint32_t code = cd[q], tcode = td[q];
+      // (bitwise & and | on the flags: no branches)
+      const bool ok = (r < g.bh) & (col < g.bw) & (code != kNoData);
+      const uint32_t d = code & 7u;
+      const int dr = ddr_t(d), dc = ddc_t(d);
+      const int ta = r / TS, tb = col / TS;
+      const int th = min(TS, g.bh - ta * TS), tw = min(TS, g.bw - tb * TS);
+      const int tr = r - ta * TS + dr, tc = col - tb * TS + dc;
+      const bool drains = ok & (code < 8u);
+      const bool inside = drains & ((unsigned)tr < (unsigned)th) & ((unsigned)tc < (unsigned)tw);
+      bad |= ok & ((code > 8u) | (drains & (tcode == kNoData)));
+      if (border) {
+        // local row / column of the target against the DEM's edges
+        const int gr = r + dr, gc = col + dc;
+        bad |= drains & !inside &
+               (((g.y0 == 0) & (gr < 0)) | ((g.y0 + BH >= g.dm.H) & (gr >= g.bh)) | ((g.x0 == 0) & (gc < 0)) |
+                ((g.x0 + BW >= g.dm.W) & (gc >= g.bw)));
+      }
+      const bool has1 = inside & (tcode != kNoData);
+      // the target's own in-tile target, by the same rule
+      const uint32_t e = tcode & 7u;
+      const int ur = tr + ddr_t(e), uc = tc + ddc_t(e);
+      const bool has2 = has1 & (tcode < 8u) & ((unsigned)ur < (unsigned)th) & ((unsigned)uc < (unsigned)tw) &
+                        (ud[q] != kNoData);
+      a1[k] = has1 ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
+      a[k] = has2 ? (uint16_t)(c + (dr + ddr_t(e)) * BW + dc + ddc_t(e)) : kNoAnc;
+      more |= has2;
+      if constexpr (kCount)
+        v0[k] = ok ? 1u : 0u;
+      else
+        v0[k] = ok ? (double)wv[k] : 0.0;
+      sm.val[c] = v0[k];
+      const uint16_t root = has2 ? a[k] : (has1 ? a1[k] : (uint16_t)c);
+      sm.link[c] = (uint32_t)a[k] | ((uint32_t)root << 16);
+    }
   }
-  __syncthreads();
-  D8_STAMP(0, 2);
-
-  // Doubling rounds.  Reads of a round (own value, ancestor's link word) all
-  // happen before the barrier, updates after it.  The saturating pointer
-  // becomes the ancestor's saturating pointer when the exact one runs out.
-  const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
+  if (bad) set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
   __shared__ RoundFlag rf;
   if (threadIdx.x == 0) rf.f[0] = rf.f[1] = 0;
   __syncthreads();
-  for (int round = 0;; ++round) {
+  D8_STAMP(0, 2);
+
+  // Round 0 of the doubling: every cell adds its initial value to its target
+  // (the links already name the distance-2 ancestors).
+#pragma unroll
+  for (int k = 0; k < CPT; ++k)
+    if (a1[k] != kNoAnc) atomicAdd(&sm.val[a1[k]], v0[k]);
+  if (more) rf.f[0] = 1;
+  __syncthreads();
+
+  // Rounds 1, 2, ...  Reads of a round (own value, ancestor's link word) all
+  // happen before the barrier, updates after it.  The saturating pointer
+  // becomes the ancestor's saturating pointer when the exact one runs out.
+  const int max_rounds = 2 + 31 - __builtin_clz((unsigned)(TS * TS));
+  for (int round = 1; rf.f[(round - 1) & 1]; ++round) {
+    if (round > max_rounds) {
+      set_status(status, kStCycle);  // a cycle never runs out of ancestors
+      break;
+    }
     V v[CPT];
     uint32_t nl[CPT];
 #pragma unroll
@@ -498,7 +558,6 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
     }
     __syncthreads();
     if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
-    bool more = false;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
@@ -507,16 +566,14 @@ __global__ __launch_bounds__(BW * BH / CPT) void k_block_emit(
         const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
         a[k] = na;
         sm.link[tid + k * NT] = (uint32_t)na | (root << 16);
-        more |= na != kNoAnc;
       }
     }
-    if (more) rf.f[round & 1] = 1;
+    // any ancestor left: the AND of the pointers is kNoAnc only if all are
+    uint32_t all = kNoAnc;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) all &= a[k];
+    if (all != kNoAnc) rf.f[round & 1] = 1;
     __syncthreads();
-    if (!rf.f[round & 1]) break;
-    if (round >= max_rounds) {
-      set_status(status, kStCycle);  // a cycle never runs out of ancestors
-      break;
-    }
   }
   __syncthreads();
   D8_STAMP(0, 3);
