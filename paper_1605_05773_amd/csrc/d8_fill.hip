@@ -114,12 +114,90 @@ __device__ __forceinline__ void fill_enqueue(const FillArgs& a, uint32_t t, uint
   }
 }
 
+// One set of sweeps of a tile, the part of wave DIR (0: rows top to bottom,
+// 1: rows bottom to top, 2: columns left to right, 3: columns right to left).
+// The wave walks its 64 lines one per step, lane x at position x of the line.
+// It keeps three lines in registers: the previous one as this wave left it (a
+// lane's neighbours there come from the adjacent lanes by DPP wave shifts,
+// the edge lanes keeping their halo cell), the current one and the next one.
+// Each step reads the line two ahead (three keys per lane, issued a step
+// before they are needed) and the key of z.  Values read earlier may be
+// higher than the current ones (other waves lower them meanwhile); every key
+// is an upper bound of the fixed point at all times, and a set that changes
+// nothing reads a constant array, so the result is the same.  Cells that are
+// NaN or outside the DEM have z key kKeyNone, which no candidate beats, so
+// the step needs no validity test.  Returns whether a cell was lowered.
+template <int DIR>
+__device__ __forceinline__ bool sweep_lines(uint32_t* K, const uint32_t* Zk, uint32_t* moved, int lane, float eps) {
+  constexpr bool kRows = DIR < 2;
+  constexpr int sg = (DIR == 0 || DIR == 2) ? 1 : -1;  // line step
+  constexpr int L0 = sg > 0 ? 0 : kFT - 1;              // first line
+  constexpr int ls = kRows ? kFK : 1, xs = kRows ? 1 : kFK;  // key index steps: line, position
+  constexpr int zls = kRows ? kFZ : 1, zxs = kRows ? 1 : kFZ;
+  // key of FLT_MAX: inc of it is +inf, as inc of +inf is, so candidates from
+  // no or unreached neighbours need no test of their own
+  constexpr uint32_t kKeyMax = 0xFF7FFFFFu;
+  // key index of line L0, position lane (lines and positions -1 and kFT: halo)
+  const int b0 = (L0 + 1) * ls + (lane + 1) * xs;
+  uint32_t p1 = K[b0 - sg * ls], p0 = K[b0 - sg * ls - xs], p2 = K[b0 - sg * ls + xs];
+  uint32_t c1 = K[b0], c0 = K[b0 - xs], c2 = K[b0 + xs];
+  uint32_t n1 = K[b0 + sg * ls], n0 = K[b0 + sg * ls - xs], n2 = K[b0 + sg * ls + xs];
+  int ci = b0;                       // the current cell
+  int zi = L0 * zls + lane * zxs;    // its z key
+  uint32_t kzn = Zk[zi];
+  bool any = false;
+#pragma unroll 4
+  for (int s = 0; s < kFT; ++s) {
+    // the line two ahead (the halo line, then the spare row, at the end)
+    const int fi = ci + 2 * sg * ls;
+    const uint32_t f0 = K[fi - xs], f1 = K[fi], f2 = K[fi + xs];
+    const uint32_t kz = kzn;
+    kzn = Zk[zi + sg * zls];
+    const uint32_t cur = c1;
+    const uint32_t mo = min(min(min(c0, c2), min(n0, n1)), min(n2, kKeyMax));  // known a step early
+    const uint32_t m = min(min(p0, p1), min(p2, mo));
+    const float x = fval(m);
+    const float y = x + eps;
+    const uint32_t ux = __float_as_uint(x);
+    const float xi = y > x ? y : __uint_as_float(x > 0.0f ? ux + 1u : ux - 1u);  // inc_eps(x), x finite
+    const uint32_t ki = fkey(xi);
+    const uint32_t nk = kz > ki ? kz : ki;
+    const bool lower = nk < cur;
+    if (lower) {
+      const int l = L0 + sg * s;
+      const int r = kRows ? l : lane, c = kRows ? lane : l;
+      atomicMin(&K[ci], nk);
+      atomicOr(&moved[(r * kFT + c) >> 5], 1u << (c & 31));
+    }
+    any |= lower;
+    const uint32_t nc = lower ? nk : cur;  // the cell's key after this step
+    // the line just done becomes the previous one, the next the current
+    p1 = nc;
+    p0 = (uint32_t)__builtin_amdgcn_update_dpp((int)c0, (int)nc, 0x138, 0xF, 0xF, false);  // wave_shr:1
+    p2 = (uint32_t)__builtin_amdgcn_update_dpp((int)c2, (int)nc, 0x130, 0xF, 0xF, false);  // wave_shl:1
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    n0 = f0;
+    n1 = f1;
+    n2 = f2;
+    ci += sg * ls;
+    zi += sg * zls;
+  }
+  return any;
+}
+
 // One round over the queued tiles (FIRST: every tile, with F initialised from
 // z in the tile: seeds = z, other valid cells +inf).
 template <bool FIRST>
 __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t round) {
-  __shared__ uint32_t K[(kFT + 2) * kFK];
-  __shared__ float Z[kFT * kFZ];
+  // Keys of the tile and its halo ring, and keys of z (kKeyNone: NaN or
+  // outside the DEM), each with one spare row before and after, which the
+  // sweeps' read-ahead touches at their last step (and then ignores).
+  __shared__ uint32_t Kraw[(kFT + 4) * kFK];
+  __shared__ uint32_t Zraw[(kFT + 2) * kFZ];
+  uint32_t* const K = Kraw + kFK;
+  uint32_t* const Zk = Zraw + kFZ;
   __shared__ uint32_t chg[3];
   __shared__ uint32_t sides;
   __shared__ uint32_t moved[kFT * kFT / 32];  // cells lowered during this visit
@@ -173,7 +251,7 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
 #pragma unroll
       for (int p = 0; p < kTR; ++p) zv[p] = (cx && 4 * p + w < th) ? p0[(int64_t)(4 * p) * W] : __builtin_nanf("");
 #pragma unroll
-      for (int p = 0; p < kTR; ++p) Z[(4 * p + w) * kFZ + lane] = zv[p];
+      for (int p = 0; p < kTR; ++p) Zk[(4 * p + w) * kFZ + lane] = __builtin_isnan(zv[p]) ? kKeyNone : fkey(zv[p]);
     }
     __syncthreads();
     if (FIRST) {
@@ -198,7 +276,7 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         }
         ik[p] = key;
         known |= key < kKeyInf;
-        Z[r * kFZ + c] = zc;
+        Zk[r * kFZ + c] = __builtin_isnan(zc) ? kKeyNone : fkey(zc);
       }
       uint32_t ring[2];
 #pragma unroll
@@ -234,39 +312,15 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
     for (int it = 0; known; ++it) {
       ++sets;
       if (tid == 0) chg[(it + 1) % 3] = 0;
-      bool any = false;
-      // One LDS round trip per step: the cell's key and its eight neighbours'
-      // are read together; z (read-only) is fetched one step ahead.
-      const int r0 = w == 0 ? 0 : w == 1 ? kFT - 1 : lane;
-      const int c0 = w == 2 ? 0 : w == 3 ? kFT - 1 : lane;
-      const int dh = w == 0 ? kFK : w == 1 ? -kFK : w == 2 ? 1 : -1;    // key step
-      const int dz = w == 0 ? kFZ : w == 1 ? -kFZ : w == 2 ? 1 : -1;    // z step
-      const bool along_rows = w < 2;
-      int h = (r0 + 1) * kFK + c0 + 1, hz = r0 * kFZ + c0;
-      float zn = Z[hz];
-      for (int s = 0; s < kFT; ++s) {
-        const float zc = zn;
-        if (s + 1 < kFT) zn = Z[hz + dz];
-        const int r = along_rows ? (w == 0 ? s : kFT - 1 - s) : lane;
-        const int c = along_rows ? lane : (w == 2 ? s : kFT - 1 - s);
-        if (r < th && c < tw && !__builtin_isnan(zc)) {
-          const uint32_t cur = K[h];
-          uint32_t m = min(min(K[h - kFK - 1], K[h - kFK]), min(K[h - kFK + 1], K[h - 1]));
-          m = min(min(m, kKeyInf), min(min(K[h + 1], K[h + kFK - 1]), min(K[h + kFK], K[h + kFK + 1])));
-          const uint32_t kz = fkey(zc);
-          if (cur != kz) {
-            const uint32_t ki = fkey(inc_eps(fval(m), eps));
-            const uint32_t nk = kz > ki ? kz : ki;
-            if (nk < cur) {
-              atomicMin(&K[h], nk);
-              atomicOr(&moved[(r * kFT + c) >> 5], 1u << (c & 31));
-              any = true;
-            }
-          }
-        }
-        h += dh;
-        hz += dz;
-      }
+      bool any;  // this wave lowered a cell
+      if (w == 0)
+        any = sweep_lines<0>(K, Zk, moved, lane, eps);
+      else if (w == 1)
+        any = sweep_lines<1>(K, Zk, moved, lane, eps);
+      else if (w == 2)
+        any = sweep_lines<2>(K, Zk, moved, lane, eps);
+      else
+        any = sweep_lines<3>(K, Zk, moved, lane, eps);
       if (any) chg[it % 3] = 1;
       __syncthreads();
       if (!chg[it % 3]) break;
@@ -290,8 +344,8 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         // first round: every finite value is new to the neighbours
         const bool mv = FIRST ? key < kKeyInf : (moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u;
         if (FIRST) {
-          const float zc = Z[r * kFZ + c];
-          *dst = __builtin_isnan(zc) ? zc : fval(key);
+          // NoData cells keep their NaN, bit for bit
+          *dst = Zk[r * kFZ + c] == kKeyNone ? a.z[(y0 + r) * W + x0 + c] : fval(key);
         } else if (mv) {
           *dst = fval(key);
         }
