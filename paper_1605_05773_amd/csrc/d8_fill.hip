@@ -349,23 +349,28 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         } else if (mv) {
           *dst = fval(key);
         }
+      }
+      // Border cells, one per thread (the row loop above would leave most
+      // lanes idle): a neighbouring tile needs another visit only if a moved
+      // cell can lower one of its cells; the halo still holds their values
+      // from the start of this visit (an upper bound of their current ones).
+      if (tid < perim_count(tw, th)) {
+        int r, c;
+        perim_cell(tid, tw, th, r, c);
+        const uint32_t key = K[(r + 1) * kFK + c + 1];
+        const bool mv = FIRST ? key < kKeyInf : ((moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u) != 0u;
         if (mv) {
-          if (r == 0 || c == 0 || r == th - 1 || c == tw - 1) {
-            // A neighbouring tile needs another visit only if this cell can
-            // lower one of its cells: the halo still holds their values from
-            // the start of this visit (an upper bound of their current ones).
-            const uint32_t ki = fkey(inc_eps(fval(key), a.eps));
+          const uint32_t ki = fkey(inc_eps(fval(key), a.eps));
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-              const int dr = d < 3 ? -1 : d < 5 ? 0 : 1;
-              const int dc = (d == 0 || d == 3 || d == 5) ? -1 : (d == 1 || d == 6) ? 0 : 1;
-              const int rq = r + dr, cq = c + dc;
-              if (rq >= 0 && rq < th && cq >= 0 && cq < tw) continue;  // inside this tile
-              const uint32_t kq = K[(rq + 1) * kFK + cq + 1];
-              if (kq == kKeyNone || kq <= ki) continue;
-              const int ny = rq < 0 ? 0 : rq >= th ? 2 : 1, nx = cq < 0 ? 0 : cq >= tw ? 2 : 1;
-              sb |= 1u << (ny * 3 + nx);
-            }
+          for (int d = 0; d < 8; ++d) {
+            const int dr = d < 3 ? -1 : d < 5 ? 0 : 1;
+            const int dc = (d == 0 || d == 3 || d == 5) ? -1 : (d == 1 || d == 6) ? 0 : 1;
+            const int rq = r + dr, cq = c + dc;
+            if (rq >= 0 && rq < th && cq >= 0 && cq < tw) continue;  // inside this tile
+            const uint32_t kq = K[(rq + 1) * kFK + cq + 1];
+            if (kq == kKeyNone || kq <= ki) continue;
+            const int ny = rq < 0 ? 0 : rq >= th ? 2 : 1, nx = cq < 0 ? 0 : cq >= tw ? 2 : 1;
+            sb |= 1u << (ny * 3 + nx);
           }
         }
       }
