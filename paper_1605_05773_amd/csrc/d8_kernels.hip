@@ -701,10 +701,26 @@ __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int
     bool live = hr[q] >= 0 && x != (V)0;
     int p = live ? hr[q] : 0;
     // bounded: a cycle never ends
+    V xc = x;  // what this lane carries (its own inflow and any it absorbed)
+    const uint32_t lane = threadIdx.x & 63u;
     for (int n = 0; n < NC && __builtin_amdgcn_ballot_w64(live); ++n) {
       const uint32_t k = code[p];
+      if constexpr (std::is_same<V, uint32_t>::value) {
+        // Two lanes at the same cell at the same step follow the same path
+        // from here on: the right one of an adjacent lane pair hands its
+        // value to the left one and stops.  Pairs alternate by step
+        // ((0,1), (2,3), ... then (1,2), (3,4), ...), so a lane is never
+        // both absorbing and absorbed in one step.
+        const int pk = live ? p : -1;
+        const int pl = __builtin_amdgcn_update_dpp(-1, pk, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
+        const bool right = ((lane + (uint32_t)n) & 1u) != 0u;
+        const bool dup = right & live & (pl == p);
+        const uint32_t give = dup ? xc : 0u;
+        xc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // from lane + 1 (wave_shl:1)
+        live = live & !dup;
+      }
       const bool add = live & (k < kOutside);  // not a NoData target (flagged by the emit pass)
-      if (add) atomicAdd(&Y[p], x);
+      if (add) atomicAdd(&Y[p], xc);
       // on to the next cell unless this one is an outlet, an exit of the tile
       // (marked as an outlet) or carries an invalid code (flagged by the emit
       // pass)
