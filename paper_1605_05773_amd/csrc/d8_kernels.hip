@@ -705,7 +705,7 @@ __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int
     const uint32_t lane = threadIdx.x & 63u;
     for (int n = 0; n < NC && __builtin_amdgcn_ballot_w64(live); ++n) {
       const uint32_t k = code[p];
-      if constexpr (std::is_same<V, uint32_t>::value) {
+      {
         // Two lanes at the same cell at the same step follow the same path
         // from here on: the right one of an adjacent lane pair hands its
         // value to the left one and stops.  Pairs alternate by step
@@ -715,8 +715,15 @@ __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int
         const int pl = __builtin_amdgcn_update_dpp(-1, pk, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
         const bool right = ((lane + (uint32_t)n) & 1u) != 0u;
         const bool dup = right & live & (pl == p);
-        const uint32_t give = dup ? xc : 0u;
-        xc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // from lane + 1 (wave_shl:1)
+        const V give = dup ? xc : (V)0;
+        if constexpr (std::is_same<V, uint32_t>::value) {
+          xc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // from lane + 1 (wave_shl:1)
+        } else {
+          const uint64_t gb = __builtin_bit_cast(uint64_t, give);
+          const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)gb, 0x130, 0xF, 0xF, false);
+          const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, false);
+          xc += __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+        }
         live = live & !dup;
       }
       const bool add = live & (k < kOutside);  // not a NoData target (flagged by the emit pass)
