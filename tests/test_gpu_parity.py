@@ -125,6 +125,36 @@ def test_counts_fixup_grouped_and_single_paths(shape):
     np.testing.assert_array_equal(gpu_counts(d, 64), oracle.accum_u32(d))
 
 
+def converging_valleys(H, W, spacing=64, offset=27):
+    """A direction field of parallel valleys: every cell drains south, towards
+    the nearest valley column diagonally (SE or SW) and straight down it, so
+    that the paths entering a tile through its top row run into the valley in
+    lockstep (two receivers reach the same valley cell at the same step, in
+    long runs) and the finalising walks merge lanes pair after pair."""
+    d = np.full((H, W), 6, dtype=np.uint8)  # S
+    c = np.arange(W)
+    ch = offset + spacing * np.round((c - offset) / spacing).astype(np.int64)
+    d[:, c < ch] = 7  # SE
+    d[:, c > ch] = 5  # SW
+    d[0, :] = d[-1, :] = 8
+    d[:, 0] = d[:, -1] = 8
+    return d
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("shape,spacing,offset", [((320, 300), 64, 27), ((257, 513), 40, 5), ((200, 130), 130, 64)])
+def test_counts_converging_walks(tile, shape, spacing, offset):
+    d = converging_valleys(*shape, spacing, offset)
+    np.testing.assert_array_equal(gpu_counts(d, tile), oracle.accum_u32(d))
+
+
+@pytest.mark.parametrize("tile", [32, 64])
+def test_weighted_converging_walks(tile):
+    d = converging_valleys(320, 300, 64, 27)
+    w = np.random.default_rng(11).lognormal(0.0, 1.0, d.shape).astype(np.float32)
+    assert_rel(gpu_weighted(d, w, tile), oracle.accum_f64(d, w), 1e-6)
+
+
 def test_counts_deterministic_and_tile_invariant():
     d = oracle.flowdirs(demgen.fbm_dem(777, 1000, sigma=5.0, seed=9))
     runs = [gpu_counts(d, t) for t in (32, 64, 64, 128)]
