@@ -226,6 +226,7 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
     }
     if (tid < kFT * kFT / 32) moved[tid] = 0;
     bool known = false;  // any key of the tile or its halo below +inf
+    bool anynan = false;  // first round: a NaN (NoData or off the DEM) in the tile or its halo
     {
       float v[kHR], e[kHR];
       load_halo_tile(FIRST ? a.z : a.F, y0, x0, H, W, v, e);
@@ -236,6 +237,7 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         if (FIRST) {  // raw z bits for the seed test below
           K[r * kFK + lane] = __float_as_uint(v[p]);
           if (lane < 2) K[r * kFK + kFT + lane] = __float_as_uint(e[p]);
+          anynan |= __builtin_isnan(v[p]) | ((lane < 2) & __builtin_isnan(e[p]));
         } else {
           K[r * kFK + lane] = __builtin_isnan(v[p]) ? kKeyNone : fkey(v[p]);
           if (lane < 2) K[r * kFK + kFT + lane] = __builtin_isnan(e[p]) ? kKeyNone : fkey(e[p]);
@@ -244,150 +246,167 @@ __global__ __launch_bounds__(kFThreads) void k_fill_round(FillArgs a, uint32_t r
         }
       }
     }
-    if (!FIRST) {
-      float zv[kTR];
-      const bool cx = lane < tw;
-      const float* p0 = a.z + (y0 + w) * W + x0 + lane;
-#pragma unroll
-      for (int p = 0; p < kTR; ++p) zv[p] = (cx && 4 * p + w < th) ? p0[(int64_t)(4 * p) * W] : __builtin_nanf("");
-#pragma unroll
-      for (int p = 0; p < kTR; ++p) Zk[(4 * p + w) * kFZ + lane] = __builtin_isnan(zv[p]) ? kKeyNone : fkey(zv[p]);
-    }
-    __syncthreads();
+    // First round: a whole tile away from the DEM's edges with no NaN in it
+    // or its halo ring holds no seed, so every cell starts at +inf and the
+    // visit has nothing else to do.
+    bool idle = false;
     if (FIRST) {
-      // Seeds (valid, on the DEM boundary or next to NaN) start at z, every
-      // other valid cell at +inf; the halo ring knows only the DEM-boundary
-      // seeds (everything else there is unknown until the next round).
-      uint32_t ik[kTR];
-#pragma unroll
-      for (int p = 0; p < kTR; ++p) {
-        const int r = 4 * p + w, c = lane;
-        const int h = (r + 1) * kFK + c + 1;
-        const float zc = __uint_as_float(K[h]);
-        uint32_t key = __builtin_isnan(zc) ? kKeyNone : kKeyInf;
-        if (r < th && c < tw && !__builtin_isnan(zc)) {
-          const int64_t gy = y0 + r, gx = x0 + c;
-          bool seed = gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1;
-          seed |= __builtin_isnan(__uint_as_float(K[h + 1])) || __builtin_isnan(__uint_as_float(K[h - 1])) ||
-                  __builtin_isnan(__uint_as_float(K[h - kFK - 1])) || __builtin_isnan(__uint_as_float(K[h - kFK])) ||
-                  __builtin_isnan(__uint_as_float(K[h - kFK + 1])) || __builtin_isnan(__uint_as_float(K[h + kFK - 1])) ||
-                  __builtin_isnan(__uint_as_float(K[h + kFK])) || __builtin_isnan(__uint_as_float(K[h + kFK + 1]));
-          if (seed) key = fkey(zc);
-        }
-        ik[p] = key;
-        known |= key < kKeyInf;
-        Zk[r * kFZ + c] = __builtin_isnan(zc) ? kKeyNone : fkey(zc);
-      }
-      uint32_t ring[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int j = tid + q * kFThreads;
-        ring[q] = kKeyNone;
-        if (j < 4 * (kFT + 2) - 4) {
-          const int h = ring_index(j);
-          const int r = h / kFK, c = h - r * kFK;
-          const int64_t gy = y0 - 1 + r, gx = x0 - 1 + c;
-          const float v = __uint_as_float(K[h]);
-          if (!__builtin_isnan(v)) ring[q] = (gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1) ? fkey(v) : kKeyInf;
-          known |= ring[q] < kKeyInf;
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int p = 0; p < kTR; ++p) K[(4 * p + w + 1) * kFK + lane + 1] = ik[p];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int j = tid + q * kFThreads;
-        if (j < 4 * (kFT + 2) - 4) K[ring_index(j)] = ring[q];
-      }
+      const bool nan_near = __syncthreads_or(anynan);
+      const bool edge = y0 == 0 || x0 == 0 || y0 + kFT >= H - 1 || x0 + kFT >= W - 1;
+      idle = !edge && !nan_near;
     }
-    // A tile whose cells and halo are all unknown (+inf) cannot change.
-    known = __syncthreads_or(known);
-
-    // Directional sweeps: sets until one changes nothing, at most
-    // kFillSweepCap + 1 of them.
-    const float eps = a.eps;
-    bool capped = false;
-    int sets = 0;
-    for (int it = 0; known; ++it) {
-      ++sets;
-      if (tid == 0) chg[(it + 1) % 3] = 0;
-      bool any;  // this wave lowered a cell
-      if (w == 0)
-        any = sweep_lines<0>(K, Zk, moved, lane, eps);
-      else if (w == 1)
-        any = sweep_lines<1>(K, Zk, moved, lane, eps);
-      else if (w == 2)
-        any = sweep_lines<2>(K, Zk, moved, lane, eps);
-      else
-        any = sweep_lines<3>(K, Zk, moved, lane, eps);
-      if (any) chg[it % 3] = 1;
-      __syncthreads();
-      if (!chg[it % 3]) break;
-      if (it == kFillSweepCap) {  // the tile goes round again
-        capped = true;
-        break;
-      }
-    }
-
-    // Write back (first round: everything; later: what moved) and note which
-    // neighbours hold a moved cell in their halo.
-    uint32_t sb = 0;
-    {
+    if (idle) {
       float* p0 = a.F + (y0 + w) * W + x0 + lane;
-#pragma unroll 1
-      for (int p = 0; p < kTR; ++p) {
-        const int r = 4 * p + w, c = lane;
-        if (r >= th || c >= tw) continue;
-        const uint32_t key = K[(r + 1) * kFK + c + 1];
-        float* dst = p0 + (int64_t)(4 * p) * W;
-        // first round: every finite value is new to the neighbours
-        const bool mv = FIRST ? key < kKeyInf : (moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u;
-        if (FIRST) {
-          // NoData cells keep their NaN, bit for bit
-          *dst = Zk[r * kFZ + c] == kKeyNone ? a.z[(y0 + r) * W + x0 + c] : fval(key);
-        } else if (mv) {
-          *dst = fval(key);
+#pragma unroll
+      for (int p = 0; p < kTR; ++p) p0[(int64_t)(4 * p) * W] = __builtin_inff();
+    } else {
+      if (!FIRST) {
+        float zv[kTR];
+        const bool cx = lane < tw;
+        const float* p0 = a.z + (y0 + w) * W + x0 + lane;
+#pragma unroll
+        for (int p = 0; p < kTR; ++p) zv[p] = (cx && 4 * p + w < th) ? p0[(int64_t)(4 * p) * W] : __builtin_nanf("");
+#pragma unroll
+        for (int p = 0; p < kTR; ++p) Zk[(4 * p + w) * kFZ + lane] = __builtin_isnan(zv[p]) ? kKeyNone : fkey(zv[p]);
+      }
+      __syncthreads();
+      if (FIRST) {
+        // Seeds (valid, on the DEM boundary or next to NaN) start at z, every
+        // other valid cell at +inf; the halo ring knows only the DEM-boundary
+        // seeds (everything else there is unknown until the next round).
+        uint32_t ik[kTR];
+#pragma unroll
+        for (int p = 0; p < kTR; ++p) {
+          const int r = 4 * p + w, c = lane;
+          const int h = (r + 1) * kFK + c + 1;
+          const float zc = __uint_as_float(K[h]);
+          uint32_t key = __builtin_isnan(zc) ? kKeyNone : kKeyInf;
+          if (r < th && c < tw && !__builtin_isnan(zc)) {
+            const int64_t gy = y0 + r, gx = x0 + c;
+            bool seed = gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1;
+            seed |= __builtin_isnan(__uint_as_float(K[h + 1])) || __builtin_isnan(__uint_as_float(K[h - 1])) ||
+                    __builtin_isnan(__uint_as_float(K[h - kFK - 1])) ||
+                    __builtin_isnan(__uint_as_float(K[h - kFK])) ||
+                    __builtin_isnan(__uint_as_float(K[h - kFK + 1])) ||
+                    __builtin_isnan(__uint_as_float(K[h + kFK - 1])) ||
+                    __builtin_isnan(__uint_as_float(K[h + kFK])) || __builtin_isnan(__uint_as_float(K[h + kFK + 1]));
+            if (seed) key = fkey(zc);
+          }
+          ik[p] = key;
+          known |= key < kKeyInf;
+          Zk[r * kFZ + c] = __builtin_isnan(zc) ? kKeyNone : fkey(zc);
+        }
+        uint32_t ring[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int j = tid + q * kFThreads;
+          ring[q] = kKeyNone;
+          if (j < 4 * (kFT + 2) - 4) {
+            const int h = ring_index(j);
+            const int r = h / kFK, c = h - r * kFK;
+            const int64_t gy = y0 - 1 + r, gx = x0 - 1 + c;
+            const float v = __uint_as_float(K[h]);
+            if (!__builtin_isnan(v)) ring[q] = (gy == 0 || gx == 0 || gy == H - 1 || gx == W - 1) ? fkey(v) : kKeyInf;
+            known |= ring[q] < kKeyInf;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < kTR; ++p) K[(4 * p + w + 1) * kFK + lane + 1] = ik[p];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int j = tid + q * kFThreads;
+          if (j < 4 * (kFT + 2) - 4) K[ring_index(j)] = ring[q];
         }
       }
-      // Border cells, one per thread (the row loop above would leave most
-      // lanes idle): a neighbouring tile needs another visit only if a moved
-      // cell can lower one of its cells; the halo still holds their values
-      // from the start of this visit (an upper bound of their current ones).
-      if (tid < perim_count(tw, th)) {
-        int r, c;
-        perim_cell(tid, tw, th, r, c);
-        const uint32_t key = K[(r + 1) * kFK + c + 1];
-        const bool mv = FIRST ? key < kKeyInf : ((moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u) != 0u;
-        if (mv) {
-          const uint32_t ki = fkey(inc_eps(fval(key), a.eps));
+      // A tile whose cells and halo are all unknown (+inf) cannot change.
+      known = __syncthreads_or(known);
+
+      // Directional sweeps: sets until one changes nothing, at most
+      // kFillSweepCap + 1 of them.
+      const float eps = a.eps;
+      bool capped = false;
+      int sets = 0;
+      for (int it = 0; known; ++it) {
+        ++sets;
+        if (tid == 0) chg[(it + 1) % 3] = 0;
+        bool any;  // this wave lowered a cell
+        if (w == 0)
+          any = sweep_lines<0>(K, Zk, moved, lane, eps);
+        else if (w == 1)
+          any = sweep_lines<1>(K, Zk, moved, lane, eps);
+        else if (w == 2)
+          any = sweep_lines<2>(K, Zk, moved, lane, eps);
+        else
+          any = sweep_lines<3>(K, Zk, moved, lane, eps);
+        if (any) chg[it % 3] = 1;
+        __syncthreads();
+        if (!chg[it % 3]) break;
+        if (it == kFillSweepCap) {  // the tile goes round again
+          capped = true;
+          break;
+        }
+      }
+
+      // Write back (first round: everything; later: what moved) and note which
+      // neighbours hold a moved cell in their halo.
+      uint32_t sb = 0;
+      {
+        float* p0 = a.F + (y0 + w) * W + x0 + lane;
+#pragma unroll 1
+        for (int p = 0; p < kTR; ++p) {
+          const int r = 4 * p + w, c = lane;
+          if (r >= th || c >= tw) continue;
+          const uint32_t key = K[(r + 1) * kFK + c + 1];
+          float* dst = p0 + (int64_t)(4 * p) * W;
+          // first round: every finite value is new to the neighbours
+          const bool mv = FIRST ? key < kKeyInf : (moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u;
+          if (FIRST) {
+            // NoData cells keep their NaN, bit for bit
+            *dst = Zk[r * kFZ + c] == kKeyNone ? a.z[(y0 + r) * W + x0 + c] : fval(key);
+          } else if (mv) {
+            *dst = fval(key);
+          }
+        }
+        // Border cells, one per thread (the row loop above would leave most
+        // lanes idle): a neighbouring tile needs another visit only if a moved
+        // cell can lower one of its cells; the halo still holds their values
+        // from the start of this visit (an upper bound of their current ones).
+        if (tid < perim_count(tw, th)) {
+          int r, c;
+          perim_cell(tid, tw, th, r, c);
+          const uint32_t key = K[(r + 1) * kFK + c + 1];
+          const bool mv = FIRST ? key < kKeyInf : ((moved[(r * kFT + c) >> 5] >> (c & 31)) & 1u) != 0u;
+          if (mv) {
+            const uint32_t ki = fkey(inc_eps(fval(key), a.eps));
 #pragma unroll
-          for (int d = 0; d < 8; ++d) {
-            const int dr = d < 3 ? -1 : d < 5 ? 0 : 1;
-            const int dc = (d == 0 || d == 3 || d == 5) ? -1 : (d == 1 || d == 6) ? 0 : 1;
-            const int rq = r + dr, cq = c + dc;
-            if (rq >= 0 && rq < th && cq >= 0 && cq < tw) continue;  // inside this tile
-            const uint32_t kq = K[(rq + 1) * kFK + cq + 1];
-            if (kq == kKeyNone || kq <= ki) continue;
-            const int ny = rq < 0 ? 0 : rq >= th ? 2 : 1, nx = cq < 0 ? 0 : cq >= tw ? 2 : 1;
-            sb |= 1u << (ny * 3 + nx);
+            for (int d = 0; d < 8; ++d) {
+              const int dr = d < 3 ? -1 : d < 5 ? 0 : 1;
+              const int dc = (d == 0 || d == 3 || d == 5) ? -1 : (d == 1 || d == 6) ? 0 : 1;
+              const int rq = r + dr, cq = c + dc;
+              if (rq >= 0 && rq < th && cq >= 0 && cq < tw) continue;  // inside this tile
+              const uint32_t kq = K[(rq + 1) * kFK + cq + 1];
+              if (kq == kKeyNone || kq <= ki) continue;
+              const int ny = rq < 0 ? 0 : rq >= th ? 2 : 1, nx = cq < 0 ? 0 : cq >= tw ? 2 : 1;
+              sb |= 1u << (ny * 3 + nx);
+            }
           }
         }
       }
-    }
-    if (sb) atomicOr(&sides, sb);
-    __syncthreads();
-    // The last set still changed something: once more.  (A first-round tile
-    // whose halo guess was too high is queued by the neighbour that knows
-    // better.)
-    if (capped && tid == 0) fill_enqueue(a, t, round + 1);
-    if (tid < 9 && tid != 4) {
-      // bit 3*(dy+1) + (dx+1): the neighbouring tile at (dy, dx)
-      const int64_t ny = ty + tid / 3 - 1, nx = tx + tid % 3 - 1;
-      if ((sides >> tid) & 1u && ny >= 0 && ny < a.TY && nx >= 0 && nx < a.TX)
-        fill_enqueue(a, (uint32_t)(ny * a.TX + nx), round + 1);
-    }
-    D8_FILL_STAT(round, sets, t_start);
+      if (sb) atomicOr(&sides, sb);
+      __syncthreads();
+      // The last set still changed something: once more.  (A first-round tile
+      // whose halo guess was too high is queued by the neighbour that knows
+      // better.)
+      if (capped && tid == 0) fill_enqueue(a, t, round + 1);
+      if (tid < 9 && tid != 4) {
+        // bit 3*(dy+1) + (dx+1): the neighbouring tile at (dy, dx)
+        const int64_t ny = ty + tid / 3 - 1, nx = tx + tid % 3 - 1;
+        if ((sides >> tid) & 1u && ny >= 0 && ny < a.TY && nx >= 0 && nx < a.TX)
+          fill_enqueue(a, (uint32_t)(ny * a.TX + nx), round + 1);
+      }
+      D8_FILL_STAT(round, sets, t_start);
+    }  // not an idle first-round tile
     if (tid == 0) grab = gridDim.x + atomicAdd(&a.cnt[4 + round % 3], 1u);
     __syncthreads();  // also: LDS is reused by the next tile
     qi = grab;
