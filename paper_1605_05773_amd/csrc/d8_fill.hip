@@ -26,8 +26,8 @@
 // per lane per step), so values travel up to 64 cells along any monotone
 // run per sweep.  Updates lower a cell's key with an LDS atomic min, which
 // keeps every value an upper bound of the fixed point while the waves race.
-// A cell already at z is final (values only fall and never below z), so
-// seeds and undisturbed terrain cost two LDS reads per visit.
+// A cell already at z is final (values only fall and never below z): no
+// candidate lowers it.
 #include <algorithm>
 #include <atomic>
 
