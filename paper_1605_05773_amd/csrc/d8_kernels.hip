@@ -560,8 +560,20 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
     if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
+      bool dup = false;
+      if constexpr (kCount) {
+        // Two adjacent lanes adding to the same ancestor: the right one of the
+        // pair hands its value to the left one, which adds both at once
+        // (pairs alternate with k).
+        const int pk = a[k] != kNoAnc ? (int)a[k] : -1;
+        const int pl = __builtin_amdgcn_update_dpp(-1, pk, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
+        dup = (((tid + k) & 1) != 0) & (pk >= 0) & (pl == pk);
+        const uint32_t give = dup ? v[k] : 0u;
+        const uint32_t gain = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // lane + 1
+        if (a[k] != kNoAnc) v[k] += gain;
+      }
       if (a[k] != kNoAnc) {
-        atomicAdd(&sm.val[a[k]], v[k]);
+        if (!dup) atomicAdd(&sm.val[a[k]], v[k]);
         const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
         const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
         a[k] = na;
