@@ -302,6 +302,29 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
 // two more).  Round j sets flag[j & 1] after the middle barrier; thread 0
 // clears flag[(j + 1) & 1], which every thread finished reading before that
 // barrier.
+// Lanes of a wave that add to the same LDS address in one instruction
+// serialise.  For a pair of adjacent lanes (the right lane odd when `right`
+// says so) adding to the same target, the right lane hands its value to the
+// left one by DPP and skips its add; returns true for such a right lane.
+// target < 0: the lane adds nothing.  Every lane of the wave must call it.
+template <typename V>
+__device__ __forceinline__ bool merge_pair_add(int target, bool right, V& v) {
+  const int tl = __builtin_amdgcn_update_dpp(-1, target, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
+  const bool dup = right & (target >= 0) & (tl == target);
+  const V give = dup ? v : (V)0;
+  V gain;
+  if constexpr (sizeof(V) == 4) {
+    gain = __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, give), 0x130, 0xF, 0xF, false));
+  } else {
+    const uint64_t gb = __builtin_bit_cast(uint64_t, give);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)gb, 0x130, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, false);
+    gain = __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);  // lane + 1 (wave_shl:1)
+  }
+  if (target >= 0) v += gain;
+  return dup;
+}
+
 struct RoundFlag {
   uint32_t f[2];
 };
@@ -560,18 +583,9 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
     if (threadIdx.x == 0) rf.f[(round + 1) & 1] = 0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-      bool dup = false;
-      if constexpr (kCount) {
-        // Two adjacent lanes adding to the same ancestor: the right one of the
-        // pair hands its value to the left one, which adds both at once
-        // (pairs alternate with k).
-        const int pk = a[k] != kNoAnc ? (int)a[k] : -1;
-        const int pl = __builtin_amdgcn_update_dpp(-1, pk, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
-        dup = (((tid + k) & 1) != 0) & (pk >= 0) & (pl == pk);
-        const uint32_t give = dup ? v[k] : 0u;
-        const uint32_t gain = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // lane + 1
-        if (a[k] != kNoAnc) v[k] += gain;
-      }
+      // two adjacent lanes adding to the same ancestor add once (pairs
+      // alternate with k)
+      const bool dup = merge_pair_add<V>(a[k] != kNoAnc ? (int)a[k] : -1, ((tid + k) & 1) != 0, v[k]);
       if (a[k] != kNoAnc) {
         if (!dup) atomicAdd(&sm.val[a[k]], v[k]);
         const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
@@ -1413,8 +1427,10 @@ __global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, i
     bool more = false;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
+      // two adjacent lanes adding to the same exit add once
+      const bool dup = merge_pair_add<LV>(a[k] != kNoAnc ? (int)a[k] : -1, ((tid + k) & 1) != 0, v[k]);
       if (a[k] != kNoAnc) {
-        ladd(&val[a[k]], v[k]);
+        if (!dup) ladd(&val[a[k]], v[k]);
         const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
         const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
         a[k] = na;
