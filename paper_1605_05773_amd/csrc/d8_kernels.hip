@@ -1427,10 +1427,8 @@ __global__ __launch_bounds__(TS <= 64 ? 1024 : 512) void k_group(DemTable tab, i
     bool more = false;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      // two adjacent lanes adding to the same exit add once
-      const bool dup = merge_pair_add<LV>(a[k] != kNoAnc ? (int)a[k] : -1, ((tid + k) & 1) != 0, v[k]);
       if (a[k] != kNoAnc) {
-        if (!dup) ladd(&val[a[k]], v[k]);
+        ladd(&val[a[k]], v[k]);
         const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
         const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
         a[k] = na;
