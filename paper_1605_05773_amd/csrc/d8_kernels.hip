@@ -303,25 +303,27 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
 // clears flag[(j + 1) & 1], which every thread finished reading before that
 // barrier.
 // Lanes of a wave that add to the same LDS address in one instruction
-// serialise.  For a pair of adjacent lanes (the right lane odd when `right`
-// says so) adding to the same target, the right lane hands its value to the
-// left one by DPP and skips its add; returns true for such a right lane.
-// target < 0: the lane adds nothing.  Every lane of the wave must call it.
+// serialise.  For a pair of adjacent lanes adding to the same target, the
+// right lane (`right`; never lane 0 of the wave) hands its value to the left
+// one by DPP and skips its add; returns true for such a right lane.  Lanes
+// with `valid` false add nothing.  Every lane of the wave must call it.  The
+// shifts write 0 where the source lane is beyond the wave (bound_ctrl), so
+// lane 63, which has no right neighbour, gains 0.
 template <typename V>
-__device__ __forceinline__ bool merge_pair_add(int target, bool right, V& v) {
-  const int tl = __builtin_amdgcn_update_dpp(-1, target, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
-  const bool dup = right & (target >= 0) & (tl == target);
+__device__ __forceinline__ bool merge_pair_add(uint32_t target, bool valid, bool right, V& v) {
+  const uint32_t tl = (uint32_t)__builtin_amdgcn_mov_dpp((int)target, 0x138, 0xF, 0xF, true);  // lane - 1 (wave_shr:1)
+  const bool dup = right & valid & (tl == target);
   const V give = dup ? v : (V)0;
   V gain;
   if constexpr (sizeof(V) == 4) {
-    gain = __builtin_bit_cast(V, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, give), 0x130, 0xF, 0xF, false));
+    gain = __builtin_bit_cast(V, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, give), 0x130, 0xF, 0xF, true));
   } else {
     const uint64_t gb = __builtin_bit_cast(uint64_t, give);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)gb, 0x130, 0xF, 0xF, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, false);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)gb, 0x130, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, true);
     gain = __builtin_bit_cast(V, ((uint64_t)hi << 32) | lo);  // lane + 1 (wave_shl:1)
   }
-  if (target >= 0) v += gain;
+  if (valid) v += gain;
   return dup;
 }
 
@@ -344,7 +346,9 @@ constexpr uint16_t kNoAnc = 0xFFFF;
 // Per cell: value, and a link word (low 16 bits: the exact 2^j-th in-tile
 // ancestor or kNoAnc; high 16 bits: the ancestor at distance
 // min(2^j, distance to the tile root), i.e. the root once the exact
-// ancestor has run out).
+// ancestor has run out).  The tile pass keeps both halves as byte offsets
+// into the link array (4 x the cell index: below 2^16 for blocks of up to
+// 16384 cells, and never kNoAnc), so that a pointer is an LDS address.
 template <int BW, int BH, typename V>
 struct DblSmem {
   union {
@@ -477,7 +481,9 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
   // Cells are taken in batches of SB (register pressure).
   constexpr int SB = CPT < 4 ? CPT : 4;
   bool bad = false;
-  uint16_t a[CPT], a1[CPT];
+  static_assert(BW * BH <= 16384, "link offsets in 16 bits");
+  uint32_t a[CPT];  // 2^j-th ancestor as a link byte offset, or kNoAnc
+  uint16_t a1[CPT];
   V v0[CPT];
   bool more = false;
 #pragma unroll
@@ -536,15 +542,15 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
       const bool has2 = has1 & (tcode < 8u) & ((unsigned)ur < (unsigned)th) & ((unsigned)uc < (unsigned)tw) &
                         (ud[q] != kNoData);
       a1[k] = has1 ? (uint16_t)(c + dr * BW + dc) : kNoAnc;
-      a[k] = has2 ? (uint16_t)(c + (dr + ddr_t(e)) * BW + dc + ddc_t(e)) : kNoAnc;
+      a[k] = has2 ? 4u * (uint32_t)(c + (dr + ddr_t(e)) * BW + dc + ddc_t(e)) : (uint32_t)kNoAnc;
       more |= has2;
       if constexpr (kCount)
         v0[k] = ok ? 1u : 0u;
       else
         v0[k] = ok ? (double)wv[k] : 0.0;
       sm.val[c] = v0[k];
-      const uint16_t root = has2 ? a[k] : (has1 ? a1[k] : (uint16_t)c);
-      sm.link[c] = (uint32_t)a[k] | ((uint32_t)root << 16);
+      const uint32_t root = has2 ? a[k] : 4u * (uint32_t)(has1 ? a1[k] : (uint16_t)c);
+      sm.link[c] = a[k] | (root << 16);
     }
   }
   if (bad) set_status(status, kStBadDir);  // invalid code, or a target off the grid / into NoData
@@ -576,7 +582,7 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
     for (int k = 0; k < CPT; ++k) {
       if (a[k] != kNoAnc) {
         v[k] = sm.val[tid + k * NT];
-        nl[k] = sm.link[a[k]];
+        nl[k] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(sm.link) + a[k]);
       }
     }
     __syncthreads();
@@ -584,14 +590,17 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       // two adjacent lanes adding to the same ancestor add once (pairs
-      // alternate with k)
-      const bool dup = merge_pair_add<V>(a[k] != kNoAnc ? (int)a[k] : -1, ((tid + k) & 1) != 0, v[k]);
-      if (a[k] != kNoAnc) {
-        if (!dup) atomicAdd(&sm.val[a[k]], v[k]);
-        const uint16_t na = (uint16_t)(nl[k] & 0xFFFFu);
-        const uint32_t root = na != kNoAnc ? (uint32_t)na : (nl[k] >> 16);
+      // alternate with k; lane 0 of a wave has no left neighbour)
+      const bool valid = a[k] != kNoAnc;
+      const bool right = (((tid + k) & 1) != 0) & ((tid & 63) != 0);
+      const bool dup = merge_pair_add<V>(a[k], valid, right, v[k]);
+      if (valid) {
+        if (!dup) atomicAdd(reinterpret_cast<V*>(reinterpret_cast<char*>(sm.val) + a[k] * (sizeof(V) / 4)), v[k]);
+        // the new exact ancestor; once it runs out, the ancestor's word as a
+        // whole (its exact half is kNoAnc too, its high half the root)
+        const uint32_t na = nl[k] & 0xFFFFu;
         a[k] = na;
-        sm.link[tid + k * NT] = (uint32_t)na | (root << 16);
+        sm.link[tid + k * NT] = na == kNoAnc ? nl[k] : na * 0x10001u;
       }
     }
     // any ancestor left: the AND of the pointers is kNoAnc only if all are
@@ -651,7 +660,7 @@ __global__ __launch_bounds__(BW * BH / CPT) __attribute__((amdgpu_waves_per_eu(C
       if (code != kNoData && (input_mask<BW>(sm.code, r, col) & outside_dirs(lr, lc, twc, thc))) {
         // Receiver: the root of its in-tile path is the exit it leaves by,
         // unless the path ends at an outlet.
-        const int root = (int)(sm.link[r * BW + col] >> 16);
+        const int root = (int)(sm.link[r * BW + col] >> 18);  // byte offset / 4
         const int R = root / BW, C = root % BW;
         const uint32_t k2 = sm.code[(R + 1) * HS + C + 1];
         uint16_t link = 0xFFFF;
