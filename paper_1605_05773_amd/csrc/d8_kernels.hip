@@ -297,11 +297,6 @@ __device__ __forceinline__ V gather_inflow(const V* __restrict__ F, uint32_t ext
   return x;
 }
 
-// Termination flags of the doubling loops: two LDS words used alternately,
-// so each round needs only its two barriers (a reduction barrier would add
-// two more).  Round j sets flag[j & 1] after the middle barrier; thread 0
-// clears flag[(j + 1) & 1], which every thread finished reading before that
-// barrier.
 // Lanes of a wave that add to the same LDS address in one instruction
 // serialise.  For a pair of adjacent lanes adding to the same target, the
 // right lane (`right`; never lane 0 of the wave) hands its value to the left
@@ -327,6 +322,11 @@ __device__ __forceinline__ bool merge_pair_add(uint32_t target, bool valid, bool
   return dup;
 }
 
+// Termination flags of the doubling loops: two LDS words used alternately,
+// so each round needs only its two barriers (a reduction barrier would add
+// two more).  Round j sets flag[j & 1] after the middle barrier; thread 0
+// clears flag[(j + 1) & 1], which every thread finished reading before that
+// barrier.
 struct RoundFlag {
   uint32_t f[2];
 };
