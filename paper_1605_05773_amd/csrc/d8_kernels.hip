@@ -738,6 +738,10 @@ __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int
     // bounded: a cycle never ends
     V xc = x;  // what this lane carries (its own inflow and any it absorbed)
     const uint32_t lane = threadIdx.x & 63u;
+    // right lanes of the pairs on even and on odd steps (lane 0 of the wave
+    // has no left neighbour)
+    const bool right_even = (lane & 1u) != 0u;
+    const bool right_odd = ((lane & 1u) == 0u) & (lane != 0u);
     for (int n = 0; n < NC && __builtin_amdgcn_ballot_w64(live); ++n) {
       const uint32_t k = code[p];
       {
@@ -745,18 +749,20 @@ __device__ __forceinline__ void fixup_walks(const uint8_t* code, V* Y, const int
         // from here on: the right one of an adjacent lane pair hands its
         // value to the left one and stops.  Pairs alternate by step
         // ((0,1), (2,3), ... then (1,2), (3,4), ...), so a lane is never
-        // both absorbing and absorbed in one step.
+        // both absorbing and absorbed in one step.  The shifts write 0 where
+        // the source lane is beyond the wave (bound_ctrl): lane 0 is never a
+        // right lane, and lane 63 gains 0.
         const int pk = live ? p : -1;
-        const int pl = __builtin_amdgcn_update_dpp(-1, pk, 0x138, 0xF, 0xF, false);  // lane - 1 (wave_shr:1)
-        const bool right = ((lane + (uint32_t)n) & 1u) != 0u;
+        const int pl = __builtin_amdgcn_mov_dpp(pk, 0x138, 0xF, 0xF, true);  // lane - 1 (wave_shr:1)
+        const bool right = (n & 1) ? right_odd : right_even;
         const bool dup = right & live & (pl == p);
         const V give = dup ? xc : (V)0;
         if constexpr (std::is_same<V, uint32_t>::value) {
-          xc += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)give, 0x130, 0xF, 0xF, false);  // from lane + 1 (wave_shl:1)
+          xc += (uint32_t)__builtin_amdgcn_mov_dpp((int)give, 0x130, 0xF, 0xF, true);  // from lane + 1 (wave_shl:1)
         } else {
           const uint64_t gb = __builtin_bit_cast(uint64_t, give);
-          const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)gb, 0x130, 0xF, 0xF, false);
-          const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, false);
+          const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)gb, 0x130, 0xF, 0xF, true);
+          const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(gb >> 32), 0x130, 0xF, 0xF, true);
           xc += __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
         }
         live = live & !dup;
