@@ -1665,27 +1665,42 @@ __global__ void k_l2_walk(int32_t* par, V* val, V* acc, uint64_t* pend, const ui
   if (!leaf) return;
   int32_t s = (int32_t)i;
   V v = val[s];
-  for (int step = 0;; ++step) {
-    const int32_t pa = par[s];
-    if (pa < 0) break;
-    if (step == kL2Steps) {
-      par[s] = -(pa + 2);  // parked: finished, not yet added to its parent
-      break;
-    }
-    if constexpr (std::is_same<V, uint64_t>::value) {
+  if constexpr (std::is_same<V, uint64_t>::value) {
+    // A node's own value and parent change only by the walk that arrives at
+    // it last, so the parent's are read together with the atomic (one round
+    // trip per step, not three); they are used only by that last walk.
+    int32_t pa = par[s];
+    for (int step = 0; pa >= 0; ++step) {
+      if (step == kL2Steps) {
+        par[s] = -(pa + 2);  // parked: finished, not yet added to its parent
+        break;
+      }
+      const V vp = val[pa];
+      const int32_t pp = par[pa];
       const uint64_t old = atomicAdd(&acc[pa], v - kL2One);
       if ((old >> kL2Shift) != 1) break;
-      v = val[pa] + (old & kL2Mask) + v;
-    } else {
+      v = vp + (old & kL2Mask) + v;
+      val[pa] = v;
+      s = pa;
+      pa = pp;
+    }
+  } else {
+    for (int step = 0;; ++step) {
+      const int32_t pa = par[s];
+      if (pa < 0) break;
+      if (step == kL2Steps) {
+        par[s] = -(pa + 2);  // parked: finished, not yet added to its parent
+        break;
+      }
       unsafeAtomicAdd(&acc[pa], v);
       __threadfence();
       const uint32_t old = atomicSub(reinterpret_cast<uint32_t*>(&pend[pa]), 1u);
       if ((old & ~kL2HasKids) != 1u) break;
       __threadfence();
       v = val[pa] + __hip_atomic_load(&acc[pa], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      val[pa] = v;
+      s = pa;
     }
-    val[pa] = v;
-    s = pa;
   }
 }
 
